@@ -1,0 +1,119 @@
+"""Pins of the oracle's moment transform, equilibrium, source term and
+relaxation (Eqs. 2-4, 6, 8, 14) against textbook forms written in velocity
+space and against invariants of the collision."""
+import numpy as np
+import pytest
+
+from oracle import coexist, stepper
+
+# Textbook D2Q9 set in the order rest, +x, +y, -x, -y, then the diagonals.
+E = np.array([[0, 0], [1, 0], [0, 1], [-1, 0], [0, -1], [1, 1], [-1, 1], [-1, -1], [1, -1]])
+W = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+
+
+def textbook_feq(rho, v):
+    """Second-order Maxwell-Boltzmann equilibrium of the D2Q9 lattice."""
+    eu = E @ v
+    return W * rho * (1 + 3 * eu + 4.5 * eu ** 2 - 1.5 * (v @ v))
+
+
+def guo_forcing(v, F):
+    """Guo, Zheng and Shi's discrete forcing term w_a [3 (e_a - v).F + 9 (e_a.v)(e_a.F)]."""
+    return W * (3 * ((E - v) @ F) + 9 * (E @ v) * (E @ F))
+
+
+def test_velocity_order():
+    assert np.array_equal(stepper.velocities(), E)
+
+
+def test_transform_is_orthogonal_with_integer_rows():
+    M, Minv = stepper.transform()
+    assert np.array_equal(M, np.round(M))
+    G = M @ M.T
+    assert np.array_equal(G, np.diag(np.diag(G)))
+    assert np.allclose(M @ Minv, np.eye(9), atol=1e-15)
+
+
+def test_equilibrium_moments_are_moments_of_textbook_feq():
+    """Eq. 4 must equal M applied to the textbook equilibrium for any rho, v;
+    a wrong sign or a swapped row of M fails this."""
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        rho = rng.uniform(0.001, 0.5)
+        v = rng.uniform(-0.2, 0.2, 2)
+        m = stepper.moments(textbook_feq(rho, v))
+        meq = stepper.equilibrium_moments(rho, v[0], v[1])
+        assert np.allclose(m, meq, rtol=0, atol=1e-15)
+
+
+def _params(rates, eps=0.0):
+    P = stepper.make_params(4, 4, coexist.temperature(0.7), eps=eps, s=rates)
+    return P
+
+
+def _random_node(rng):
+    rho = rng.uniform(0.01, 0.45)
+    f = W * rho * (1 + rng.uniform(-0.3, 0.3, 9))
+    F = rng.uniform(-1e-3, 1e-3, 2)
+    psi = rng.uniform(0.05, 0.4)
+    return f, F, psi
+
+
+@pytest.mark.parametrize("tau", [0.51, 0.6, 1.0, 1.7])
+def test_mrt_equals_bgk_with_guo_forcing_at_equal_rates(tau):
+    """With all rates equal to 1/tau and eps = 0, Eq. 3 with the source of
+    Eq. 8 is the BGK collision with Guo's forcing term."""
+    rng = np.random.default_rng(int(tau * 100))
+    P = _params([1 / tau] * 9, eps=0.0)
+    for _ in range(40):
+        f, F, psi = _random_node(rng)
+        rho = f.sum()
+        v = (E.T @ f + 0.5 * F) / rho
+        bgk = f - (f - textbook_feq(rho, v)) / tau + (1 - 0.5 / tau) * guo_forcing(v, F)
+        got = stepper.collide_node(P, f, psi, F[0], F[1])
+        assert np.allclose(got, bgk, rtol=0, atol=2e-15)
+
+
+def test_collision_conserves_mass_and_adds_the_force():
+    """For any rates: rho* = rho and j* = j + F (Eq. 6's half-force velocity
+    makes the relaxation of j exactly cancel the (1 - s_j/2) F source)."""
+    rng = np.random.default_rng(7)
+    for _ in range(40):
+        rates = rng.uniform(0.5, 1.9, 9)
+        rates[5] = rates[3]
+        P = _params(rates, eps=rng.uniform(0, 2))
+        f, F, psi = _random_node(rng)
+        out = stepper.collide_node(P, f, psi, F[0], F[1])
+        assert abs(out.sum() - f.sum()) < 1e-15
+        assert np.allclose(E.T @ out, E.T @ f + F, rtol=0, atol=1e-16)
+
+
+def test_li_term_properties():
+    """Eq. 14's extra term: it leaves mass and momentum unchanged, is linear in
+    eps, scales as 1/psi^2 and (at fixed velocity) as |F|^2."""
+    rng = np.random.default_rng(11)
+    rates = stepper.relaxation_rates(0.6)
+    for _ in range(20):
+        f, F, psi = _random_node(rng)
+        base = stepper.collide_node(_params(rates, 0.0), f, psi, F[0], F[1])
+        d1 = stepper.collide_node(_params(rates, 1.0), f, psi, F[0], F[1]) - base
+        d2 = stepper.collide_node(_params(rates, 2.0), f, psi, F[0], F[1]) - base
+        dh = stepper.collide_node(_params(rates, 1.0), f, psi / 2, F[0], F[1]) - base
+        assert np.max(np.abs(d1)) > 0
+        # the differences carry the rounding of O(0.1) populations, ~1e-17
+        assert abs(d1.sum()) < 1e-16 and np.allclose(E.T @ d1, 0, atol=1e-16)
+        assert np.allclose(d2, 2 * d1, rtol=1e-8, atol=1e-16)
+        assert np.allclose(dh, 4 * d1, rtol=1e-8, atol=1e-16)
+
+
+def test_li_term_only_touches_energy_moments():
+    """The Li term enters only the e and zeta moments (rows 1 and 2 of Eq. 14)."""
+    rng = np.random.default_rng(12)
+    rates = stepper.relaxation_rates(0.8)
+    M, _ = stepper.transform()
+    f, F, psi = _random_node(rng)
+    base = stepper.collide_node(_params(rates, 0.0), f, psi, F[0], F[1])
+    d = stepper.collide_node(_params(rates, 1.86), f, psi, F[0], F[1]) - base
+    dm = M @ d
+    assert np.allclose(np.delete(dm, [1, 2]), 0, atol=1e-15)
+    assert dm[1] > 0 and dm[2] < 0
