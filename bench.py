@@ -1,0 +1,231 @@
+"""Benchmark of the D2Q9 pseudopotential MRT lattice Boltzmann timestep on one
+MI355X.
+
+Default workload: the Laplace-law and coexistence sweep (24 instances of a
+256 x 256 periodic grid: discs of radius 20..60 at T/Tc 0.6..0.9 plus one liquid
+slab per temperature), binary32, stepped as one batch: each step is one launch
+of the psi pass and one launch of the force+collide+stream pass over the tiles
+of all 24 instances, replayed from captured HIP graphs.  A "step" advances all
+24 instances by one timestep.
+
+Prints one JSON line: aggregate MLUPS (million lattice-site updates per second),
+the roofline of the dominant kernel (HBM bytes of the stated per-site model over
+its event-timed duration), the oracle's CPU rate on a bounded sample, and the
+plain per-instance binary64 rate (one instance at a time, one launch pair per
+step, no graph, no batch) that the batched binary32 rate is compared with.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per site per launch (read 9 f and write psi / read 9 f,
+# read psi, write 9 f), by element size
+BYTES_PSI = {4: 9 * 4 + 4, 8: 9 * 8 + 8}
+BYTES_COLLIDE = {4: 9 * 4 + 4 + 9 * 4, 8: 9 * 8 + 8 + 9 * 8}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="laplace_sweep",
+                    choices=["laplace_sweep", "collapse_large"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-plain", action="store_true")
+    ap.add_argument("--variant", type=int, default=-1, help="tile variant; -1 autotunes")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def laplace_sweep_sims(L, precision, device):
+    from paper_1605_01800_amd import inputs
+    sims = []
+    for case in inputs.laplace_sweep_cases(256):
+        p = L.make_params(256, 256, T_over_Tc=case["T_over_Tc"], precision=precision, tau_nu=0.6)
+        s = L.Sim(p, device=device)
+        s.init_bubble(case["bubbles"], slab_rows=case["slab_rows"], W=5.0)
+        sims.append(s)
+    return sims
+
+
+def collapse_large_sims(L, precision, device):
+    from paper_1605_01800_amd import inputs
+    nx, ny = 8192, 4096
+    bub = inputs.non_overlapping_discs(nx, ny, [300, 200, 150], W=5.0, seed=0, walls=True)
+    p = L.make_params(nx, ny, T_over_Tc=0.6, walls=True, precision=precision, tau_nu=0.51)
+    s = L.Sim(p, device=device)
+    s.init_bubble(bub, W=5.0, delta=0.02)
+    return [s]
+
+
+def cpu_baseline(seconds):
+    """The FP64 oracle on one 256 x 256 instance of the sweep (R = 40 at
+    0.7 T_c), steps sized to take about `seconds`."""
+    from oracle import coexist, stepper
+    from oracle import build as obuild
+    obuild.ensure_built()
+    T = coexist.temperature(0.7)
+    rg, rl, _ = coexist.maxwell(T)
+    P = stepper.make_params(256, 256, T, tau_nu=0.6)
+    f = stepper.init_populations(P, stepper.init_density(P, bubbles=[(127.5, 127.5, 40.0)],
+                                                         rho_l=rl, rho_g=rg, W=5.0))
+    t0 = time.perf_counter()
+    stepper.step(P, f, 3)
+    per = (time.perf_counter() - t0) / 3
+    n = max(3, int(seconds / per))
+    t0 = time.perf_counter()
+    rc = stepper.step(P, f, n)
+    dt = time.perf_counter() - t0
+    assert rc == 0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 256 * 256 * n / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": "1 of the 24 sweep instances (256x256, R=40, 0.7 Tc), %d steps, %.1f s" % (n, dt)}
+
+
+def fp64_plain(L, device, steps):
+    """Each sweep instance in binary64, one at a time, direct launches on the
+    null stream (no graph, no batching)."""
+    import torch
+    sims = []
+    from paper_1605_01800_amd import inputs
+    null = torch.cuda.default_stream(torch.device(device))
+    for case in inputs.laplace_sweep_cases(256):
+        p = L.make_params(256, 256, T_over_Tc=case["T_over_Tc"], precision="fp64", tau_nu=0.6)
+        s = L.Sim(p, device=device, stream=null)
+        s.init_bubble(case["bubbles"], slab_rows=case["slab_rows"], W=5.0)
+        sims.append(s)
+    for s in sims:
+        s.step(5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in sims:
+        s.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for s in sims:
+        s.close()
+    return len(sims) * 256 * 256 * steps / dt / 1e6
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(got --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1605_01800_amd import lbm as L
+
+    device = "cuda:0"
+    torch.cuda.set_device(0)
+    precision = "fp32"
+    es = 4
+    if args.workload == "laplace_sweep":
+        sims = laplace_sweep_sims(L, precision, device)
+        workload = {"workload": "laplace_sweep", "instances": len(sims), "grid": "256x256",
+                    "periodic": True, "T_over_Tc": [0.6, 0.7, 0.8, 0.9], "radii": [20, 30, 40, 50, 60],
+                    "slab_rows": 128, "tau_nu": 0.6, "eps": 1.86}
+    else:
+        sims = collapse_large_sims(L, precision, device)
+        workload = {"workload": "collapse_large", "instances": 1, "grid": "8192x4096",
+                    "walls_y": True, "T_over_Tc": 0.6, "radii": [300, 200, 150], "delta": 0.02,
+                    "tau_nu": 0.51, "eps": 1.86}
+    sites = sum(s.nx * s.ny for s in sims)
+    max_tiles = sum(L.tile_count(s.params) for s in sims)
+    batch = L.Batch(precision=precision, max_instances=len(sims), max_tiles=max_tiles, device=device)
+    for s in sims:
+        batch.attach(s)
+    if args.variant >= 0:
+        batch.set_variant(args.variant)
+        variant = args.variant
+    else:
+        variant, _ = batch.autotune(reps=20)
+    workload["tile"] = L.variant_names()[variant]
+    print("# workload %s sites %d variant %s" % (args.workload, sites, workload["tile"]),
+          file=sys.stderr, flush=True)
+
+    batch.step(args.warmup)
+    batch.sync()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(batch.stream)
+    batch.step(args.steps)
+    e1.record(batch.stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    torch.cuda.synchronize()
+    for s in sims:
+        s.sync()                          # raises if a non-finite value was latched
+    mlups = sites * args.steps / (ms * 1e-3) / 1e6
+    print("# timed %d steps: %.3f ms/step, %.0f MLUPS" % (args.steps, ms / args.steps, mlups),
+          file=sys.stderr, flush=True)
+
+    # per-kernel device time: an event pair around every launch, on the batch's stream
+    nk = min(args.steps, 100)
+    ms_psi, ms_col = batch.step_timed(nk)
+    t_psi, t_col = ms_psi / nk, ms_col / nk
+    bw_psi = BYTES_PSI[es] * sites / (t_psi * 1e-3) / 1e9
+    bw_col = BYTES_COLLIDE[es] * sites / (t_col * 1e-3) / 1e9
+    dominant = ("collide_stream", t_col, bw_col, BYTES_COLLIDE[es]) if t_col >= t_psi else \
+        ("psi_pass", t_psi, bw_psi, BYTES_PSI[es])
+    print("# psi pass %.4f ms (%.0f GB/s), collide %.4f ms (%.0f GB/s)" % (t_psi, bw_psi, t_col, bw_col),
+          file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "aggregate MLUPS + %HBM roofline (FP32 batched vs FP64 plain); p50/p99 latency",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (Eq. 16 initial states)",
+        "config": workload,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dominant[0],
+            "achieved": round(dominant[2], 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(dominant[2] / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "bytes_per_site": dominant[3],
+            "launch_ms": dominant[1],
+        },
+        "kernels": {
+            "psi_pass": {"ms": t_psi, "GB_s": round(bw_psi, 1), "bytes_per_site": BYTES_PSI[es]},
+            "collide_stream": {"ms": t_col, "GB_s": round(bw_col, 1), "bytes_per_site": BYTES_COLLIDE[es]},
+            "step_model_GB_s": round((BYTES_PSI[es] + BYTES_COLLIDE[es]) * sites / (ms / args.steps * 1e-3) / 1e9, 1),
+        },
+    }
+    batch.close()
+    for s in sims:
+        s.close()
+    torch.cuda.synchronize()
+
+    if args.workload == "laplace_sweep" and not args.no_fp64_plain:
+        plain = fp64_plain(L, device, steps=40)
+        out["fp64_plain_mlups"] = round(plain, 1)
+        out["speedup_vs_fp64_plain"] = round(mlups / plain, 2)
+        print("# fp64 plain per-instance %.0f MLUPS" % plain, file=sys.stderr, flush=True)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        print("# cpu baseline %.2f MLUPS" % out["cpu_baseline"]["value"], file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,11 @@
+"""gfx950 (MI355X) implementation of the D2Q9 pseudopotential multi-relaxation-
+time lattice Boltzmann timestep of Shan et al. (arXiv:1605.01800).
+
+  lbm      -- Python binding of liblbm.so (include/lbm.h): Sim, Batch, host helpers
+  serving  -- continuous-batching request server on top of lbm.Batch
+  inputs   -- seeded synthetic workloads (bubble layouts, request traces)
+  build    -- hipcc build of liblbm.so
+
+Submodules are imported on demand so that `inputs` and `build` work without a
+GPU or a built library.
+"""

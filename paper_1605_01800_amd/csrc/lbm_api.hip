@@ -1,0 +1,921 @@
+// Host side of liblbm: the C ABI of include/lbm.h.  Instances live in
+// caller-owned device workspaces; the library allocates no device memory.
+// Steps are enqueued as captured HIP graphs of up to MAX_CHUNK steps (two
+// kernels per step plus one end-of-chunk kernel), or launched directly when
+// the stream is the null stream, which cannot be captured.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <tuple>
+#include <vector>
+
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int MAX_SIDE = 65536;
+constexpr uint64_t CKPT_MAGIC = 0x314d424c4b504b43ull;   // checkpoint image tag
+constexpr int N_STAGE = 4;                               // pinned descriptor staging slots
+
+inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t elem_size(int prec) { return prec == LBM_FP64 ? 8 : 4; }
+
+struct Layout {
+    size_t desc, tiles, f0, f1, psi, partials, flag, wall_keys, wall_run, result, total;
+    int pitch;
+    int64_t max_tiles;
+};
+
+int64_t tiles_for(int nx, int ny, int rows)
+{
+    return (int64_t)((nx + TILE_X - 1) / TILE_X) * ((ny + rows - 1) / rows);
+}
+
+Layout layout_of(const lbm_params &p)
+{
+    Layout L;
+    L.pitch = (int)round_up((size_t)p.nx, TILE_X);
+    L.max_tiles = tiles_for(p.nx, p.ny, tile_rows(0));
+    const size_t es = elem_size(p.precision);
+    const size_t plane = (size_t)L.pitch * p.ny;
+    size_t o = 0;
+    L.desc = o; o = round_up(o + sizeof(InstDev), ALIGN);
+    L.tiles = o; o = round_up(o + sizeof(Tile) * (size_t)L.max_tiles, ALIGN);
+    L.f0 = o; o = round_up(o + 9 * plane * es, ALIGN);
+    L.f1 = o; o = round_up(o + 9 * plane * es, ALIGN);
+    L.psi = o; o = round_up(o + plane * es, ALIGN);
+    L.partials = o; o = round_up(o + sizeof(double) * N_PARTIAL * (size_t)L.max_tiles, ALIGN);
+    L.flag = o; o = round_up(o + sizeof(int), ALIGN);
+    L.wall_keys = o; o = round_up(o + sizeof(unsigned long long) * MAX_CHUNK, ALIGN);
+    L.wall_run = o; o = round_up(o + 2 * sizeof(unsigned long long), ALIGN);
+    L.result = o; o = round_up(o + sizeof(double) * (N_PARTIAL + 2), ALIGN);
+    L.total = o;
+    return L;
+}
+
+int check_params(const lbm_params *p)
+{
+    if (!p) return LBM_EINVAL;
+    if (p->nx < 1 || p->ny < 1 || p->nx > MAX_SIDE || p->ny > MAX_SIDE) return LBM_EINVAL;
+    if (p->walls_y != 0 && p->walls_y != 1) return LBM_EINVAL;
+    if (p->precision < LBM_FP64 || p->precision > LBM_FP32_MIXED) return LBM_EINVAL;
+    if (!(p->G < 0) || !(p->T > 0) || !(p->b > 0) || !(p->R > 0) || !(p->a >= 0)) return LBM_EINVAL;
+    if (!isfinite(p->eps)) return LBM_EINVAL;
+    const double r[6] = {p->s_rho, p->s_e, p->s_zeta, p->s_j, p->s_q, p->s_nu};
+    for (double v : r)
+        if (!(v > 0.0 && v < 2.0)) return LBM_EINVAL;
+    return LBM_OK;
+}
+
+// Pinned staging for descriptor uploads: a ring of slots, each reusable once
+// the copy that read it has completed.
+struct Stager {
+    char *host = nullptr;
+    size_t slot_bytes = 0;
+    hipEvent_t ev[N_STAGE] = {};
+    bool used[N_STAGE] = {};
+    int next = 0;
+
+    int init(size_t bytes)
+    {
+        slot_bytes = round_up(bytes, 64);
+        if (hipHostMalloc((void **)&host, slot_bytes * N_STAGE, hipHostMallocDefault) != hipSuccess)
+            return LBM_EHIP;
+        for (int i = 0; i < N_STAGE; ++i)
+            if (hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) return LBM_EHIP;
+        return LBM_OK;
+    }
+    void release()
+    {
+        for (int i = 0; i < N_STAGE; ++i)
+            if (ev[i]) (void)hipEventDestroy(ev[i]);
+        if (host) (void)hipHostFree(host);
+        host = nullptr;
+    }
+    int upload(void *dst, const void *src, size_t bytes, hipStream_t st)
+    {
+        if (bytes > slot_bytes) return LBM_EINVAL;
+        const int k = next;
+        next = (next + 1) % N_STAGE;
+        if (used[k] && hipEventSynchronize(ev[k]) != hipSuccess) return LBM_EHIP;
+        char *slot = host + (size_t)k * slot_bytes;
+        memcpy(slot, src, bytes);
+        if (hipMemcpyAsync(dst, slot, bytes, hipMemcpyHostToDevice, st) != hipSuccess) return LBM_EHIP;
+        if (hipEventRecord(ev[k], st) != hipSuccess) return LBM_EHIP;
+        used[k] = true;
+        return LBM_OK;
+    }
+};
+
+struct GraphKey {
+    int variant, K, ntiles, ninst;
+    bool operator<(const GraphKey &o) const
+    {
+        return std::tie(variant, K, ntiles, ninst) < std::tie(o.variant, o.K, o.ntiles, o.ninst);
+    }
+};
+
+struct Batch;
+
+struct Instance {
+    lbm_params p;
+    Layout L;
+    char *ws = nullptr;
+    hipStream_t stream = nullptr;
+    InstDev desc;                 // host mirror of the device descriptor
+    InstDev *d_desc = nullptr;
+    Tile *d_tiles = nullptr;
+    int variant = 0;
+    int ntiles = 0;
+    bool tiles_dirty = true;
+    bool desc_dirty = true;
+    bool has_state = false;
+    int sticky = LBM_OK;
+    Batch *batch = nullptr;
+    Stager stager;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    // init record, kept for checkpoints
+    int n_bubbles = 0;
+    lbm_bubble bubbles[LBM_MAX_BUBBLES];
+};
+
+struct Batch {
+    int precision;
+    hipStream_t stream;
+    int max_inst;
+    int64_t max_tiles;
+    InstDev *d_descs;
+    Tile *d_tiles;
+    std::vector<Instance *> members;
+    std::vector<InstDev> descs;   // host copies in attach order
+    int ntiles = 0;
+    int variant = 0;
+    bool dirty = true;
+    Stager stager_desc, stager_tiles;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+};
+
+hipStream_t stream_of(const Instance *h);
+
+void fill_desc(Instance *h)
+{
+    const lbm_params &p = h->p;
+    InstDev &d = h->desc;
+    const size_t es = elem_size(p.precision);
+    (void)es;
+    d.f[0] = h->ws + h->L.f0;
+    d.f[1] = h->ws + h->L.f1;
+    d.psi = h->ws + h->L.psi;
+    d.partials = (double *)(h->ws + h->L.partials);
+    d.flag = (int *)(h->ws + h->L.flag);
+    d.wall_keys = (unsigned long long *)(h->ws + h->L.wall_keys);
+    d.wall_run = (unsigned long long *)(h->ws + h->L.wall_run);
+    d.result = (double *)(h->ws + h->L.result);
+    d.plane = (long long)h->L.pitch * p.ny;
+    d.nx = p.nx;
+    d.ny = p.ny;
+    d.pitch = h->L.pitch;
+    d.walls = p.walls_y;
+    d.a = p.a;
+    d.b4 = p.b / 4.0;
+    d.RT = p.R * p.T;
+    d.G = p.G;
+    d.s_e = p.s_e;
+    d.s_z = p.s_zeta;
+    d.s_q = p.s_q;
+    d.s_nu = p.s_nu;
+    d.li_e = p.s_e * 0.75 * p.eps;
+    d.li_z = p.s_zeta * 0.75 * p.eps;
+}
+
+void build_tiles(int inst_index, const lbm_params &p, int variant, std::vector<Tile> &out)
+{
+    const int rows = tile_rows(variant);
+    int k = 0;
+    for (int y0 = 0; y0 < p.ny; y0 += rows)
+        for (int x0 = 0; x0 < p.nx; x0 += TILE_X) {
+            Tile t;
+            t.inst = inst_index;
+            t.x0 = x0;
+            t.y0 = y0;
+            t.tile_index = k++;
+            out.push_back(t);
+        }
+}
+
+int hip_ok(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EHIP; }
+
+#define TRY(expr)                          \
+    do {                                   \
+        int rc__ = (expr);                 \
+        if (rc__ != LBM_OK) return rc__;   \
+    } while (0)
+
+#define TRYHIP(expr) TRY(hip_ok(expr))
+
+hipStream_t stream_of(const Instance *h) { return h->batch ? h->batch->stream : h->stream; }
+
+// Makes the instance's own device descriptor and tile list current.
+int sync_own(Instance *h)
+{
+    hipStream_t st = stream_of(h);
+    if (h->tiles_dirty) {
+        std::vector<Tile> tl;
+        build_tiles(0, h->p, h->variant, tl);
+        h->ntiles = (int)tl.size();
+        h->desc.tiles_x = (h->p.nx + TILE_X - 1) / TILE_X;
+        TRYHIP(hipMemcpyAsync(h->d_tiles, tl.data(), sizeof(Tile) * tl.size(), hipMemcpyHostToDevice, st));
+        // the pageable copy above is complete when it returns for small sizes,
+        // but make sure before the vector goes away
+        TRYHIP(hipStreamSynchronize(st));
+        h->tiles_dirty = false;
+    }
+    if (h->desc_dirty) {
+        TRY(h->stager.upload(h->d_desc, &h->desc, sizeof(InstDev), st));
+        h->desc_dirty = false;
+    }
+    return LBM_OK;
+}
+
+// Enqueues one chunk: K steps of both passes and the end-of-chunk kernel.
+int enqueue_chunk(int prec, int variant, const InstDev *d_inst, int ninst, const Tile *d_tiles,
+                  int ntiles, int K, hipStream_t st)
+{
+    for (int s = 0; s < K; ++s) {
+        TRYHIP(launch_psi_pass(prec, variant, d_inst, d_tiles, ntiles, s, st));
+        TRYHIP(launch_collide_stream(prec, variant, d_inst, d_tiles, ntiles, s, st));
+    }
+    TRYHIP(launch_chunk_end(d_inst, ninst, st));
+    return LBM_OK;
+}
+
+// Runs one chunk through a cached graph when the stream can be captured.
+int run_chunk(std::map<GraphKey, hipGraphExec_t> &cache, int prec, int variant, const InstDev *d_inst,
+              int ninst, const Tile *d_tiles, int ntiles, int K, hipStream_t st)
+{
+    if (st == nullptr) return enqueue_chunk(prec, variant, d_inst, ninst, d_tiles, ntiles, K, st);
+    GraphKey key{variant, K, ntiles, ninst};
+    auto it = cache.find(key);
+    if (it == cache.end()) {
+        hipGraph_t g = nullptr;
+        TRYHIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_chunk(prec, variant, d_inst, ninst, d_tiles, ntiles, K, st);
+        hipError_t e = hipStreamEndCapture(st, &g);
+        if (rc != LBM_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        TRYHIP(e);
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        TRYHIP(e);
+        it = cache.emplace(key, ex).first;
+    }
+    TRYHIP(hipGraphLaunch(it->second, st));
+    return LBM_OK;
+}
+
+void drop_graphs(std::map<GraphKey, hipGraphExec_t> &cache)
+{
+    for (auto &kv : cache) (void)hipGraphExecDestroy(kv.second);
+    cache.clear();
+}
+
+// Host mirror of what the end-of-chunk kernel does to a descriptor.
+void advance_mirror(InstDev &d, int n)
+{
+    d.step += n;
+    d.cur ^= (n & 1);
+}
+
+int read_latch(Instance *h)
+{
+    int flag = 0;
+    TRYHIP(hipMemcpy(&flag, h->desc.flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (flag) h->sticky = LBM_ENONFINITE;
+    return h->sticky;
+}
+
+// ---------------------------------------------------------------------------
+// batch internals
+// ---------------------------------------------------------------------------
+int batch_sync(Batch *b)
+{
+    if (b->dirty) {
+        std::vector<Tile> tl;
+        b->descs.clear();
+        for (size_t i = 0; i < b->members.size(); ++i) {
+            Instance *h = b->members[i];
+            build_tiles((int)i, h->p, b->variant, tl);
+            h->desc.tiles_x = (h->p.nx + TILE_X - 1) / TILE_X;
+            b->descs.push_back(h->desc);
+        }
+        if ((int64_t)tl.size() > b->max_tiles) return LBM_ENOMEM;
+        b->ntiles = (int)tl.size();
+        if (!tl.empty()) TRY(b->stager_tiles.upload(b->d_tiles, tl.data(), sizeof(Tile) * tl.size(), b->stream));
+        b->dirty = false;
+    } else {
+        for (size_t i = 0; i < b->members.size(); ++i) b->descs[i] = b->members[i]->desc;
+    }
+    if (!b->descs.empty())
+        TRY(b->stager_desc.upload(b->d_descs, b->descs.data(), sizeof(InstDev) * b->descs.size(), b->stream));
+    return LBM_OK;
+}
+
+// Steps the members by counts[i] steps each, MAX_CHUNK steps per chunk.
+int batch_run(Batch *b, const std::vector<int64_t> &counts, bool timed, float *ms)
+{
+    const int n = (int)b->members.size();
+    for (int i = 0; i < n; ++i) {
+        Instance *h = b->members[i];
+        if (counts[i] > 0 && !h->has_state) return LBM_ESTATE;
+        if (counts[i] > 0 && h->sticky != LBM_OK) return h->sticky;
+    }
+    std::vector<int64_t> rem(counts);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+        TRYHIP(hipEventCreate(&e0));
+        TRYHIP(hipEventCreate(&e1));
+        ms[0] = ms[1] = 0.f;
+    }
+    int rc = LBM_OK;
+    for (;;) {
+        int K = 0;
+        for (int i = 0; i < n; ++i) {
+            const int ni = (int)std::min<int64_t>(rem[i], MAX_CHUNK);
+            b->members[i]->desc.n_chunk = ni;
+            K = std::max(K, ni);
+        }
+        if (K == 0) break;
+        rc = batch_sync(b);
+        if (rc != LBM_OK) break;
+        if (!timed) {
+            rc = run_chunk(b->graphs, b->precision, b->variant, b->d_descs, n, b->d_tiles, b->ntiles, K,
+                           b->stream);
+        } else {
+            for (int s = 0; s < K && rc == LBM_OK; ++s) {
+                float t;
+                rc = hip_ok(hipEventRecord(e0, b->stream));
+                if (rc == LBM_OK) rc = hip_ok(launch_psi_pass(b->precision, b->variant, b->d_descs, b->d_tiles, b->ntiles, s, b->stream));
+                if (rc == LBM_OK) rc = hip_ok(hipEventRecord(e1, b->stream));
+                if (rc == LBM_OK) rc = hip_ok(hipEventSynchronize(e1));
+                if (rc == LBM_OK) rc = hip_ok(hipEventElapsedTime(&t, e0, e1));
+                if (rc == LBM_OK) ms[0] += t;
+                if (rc == LBM_OK) rc = hip_ok(hipEventRecord(e0, b->stream));
+                if (rc == LBM_OK) rc = hip_ok(launch_collide_stream(b->precision, b->variant, b->d_descs, b->d_tiles, b->ntiles, s, b->stream));
+                if (rc == LBM_OK) rc = hip_ok(hipEventRecord(e1, b->stream));
+                if (rc == LBM_OK) rc = hip_ok(hipEventSynchronize(e1));
+                if (rc == LBM_OK) rc = hip_ok(hipEventElapsedTime(&t, e0, e1));
+                if (rc == LBM_OK) ms[1] += t;
+            }
+            if (rc == LBM_OK) rc = hip_ok(launch_chunk_end(b->d_descs, n, b->stream));
+        }
+        if (rc != LBM_OK) break;
+        for (int i = 0; i < n; ++i) {
+            Instance *h = b->members[i];
+            const int ni = h->desc.n_chunk;
+            advance_mirror(h->desc, ni);
+            rem[i] -= ni;
+            h->desc_dirty = true;    // the instance's own descriptor copy is stale
+        }
+    }
+    for (int i = 0; i < n; ++i) b->members[i]->desc.n_chunk = 0;
+    if (timed) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    return rc;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *lbm_strerror(int status)
+{
+    switch (status) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOMEM: return "workspace or buffer too small";
+    case LBM_EHIP: return "HIP runtime error";
+    case LBM_ENONFINITE: return "non-finite density or pseudopotential (psi^2 < 0) latched";
+    case LBM_ESTATE: return "call not valid in the current state";
+    default: return "unknown status";
+    }
+}
+
+int lbm_workspace_bytes(const lbm_params *params, size_t *bytes)
+{
+    TRY(check_params(params));
+    if (!bytes) return LBM_EINVAL;
+    *bytes = layout_of(*params).total;
+    return LBM_OK;
+}
+
+int lbm_tile_count(const lbm_params *params, int64_t *max_tiles)
+{
+    TRY(check_params(params));
+    if (!max_tiles) return LBM_EINVAL;
+    *max_tiles = layout_of(*params).max_tiles;
+    return LBM_OK;
+}
+
+int lbm_create(const lbm_params *params, void *d_workspace, size_t ws_bytes, void *hip_stream,
+               void **handle)
+{
+    TRY(check_params(params));
+    if (!handle || !d_workspace) return LBM_EINVAL;
+    if ((uintptr_t)d_workspace % ALIGN) return LBM_EINVAL;
+    const Layout L = layout_of(*params);
+    if (ws_bytes < L.total) return LBM_ENOMEM;
+    Instance *h = new Instance();
+    h->p = *params;
+    h->L = L;
+    h->ws = (char *)d_workspace;
+    h->stream = (hipStream_t)hip_stream;
+    memset(&h->desc, 0, sizeof(InstDev));
+    h->d_desc = (InstDev *)(h->ws + L.desc);
+    h->d_tiles = (Tile *)(h->ws + L.tiles);
+    fill_desc(h);
+    if (h->stager.init(sizeof(InstDev)) != LBM_OK) {
+        h->stager.release();
+        delete h;
+        return LBM_EHIP;
+    }
+    *handle = h;
+    return LBM_OK;
+}
+
+void lbm_destroy(void *handle)
+{
+    Instance *h = (Instance *)handle;
+    if (!h) return;
+    if (h->batch) lbm_batch_detach(h->batch, h);
+    (void)hipStreamSynchronize(h->stream);
+    drop_graphs(h->graphs);
+    h->stager.release();
+    delete h;
+}
+
+int lbm_init_bubble(void *handle, const lbm_bubble *b, int nb, int slab_rows, double rho_l,
+                    double rho_g, double W, double delta, double noise_amp, uint64_t seed)
+{
+    Instance *h = (Instance *)handle;
+    if (!h) return LBM_EINVAL;
+    if (nb < 0 || nb > LBM_MAX_BUBBLES || (nb > 0 && !b) || slab_rows < 0) return LBM_EINVAL;
+    if (!(rho_l > 0) || !(rho_g > 0) || !(W > 0) || !isfinite(delta) || !(noise_amp >= 0) ||
+        noise_amp >= 1.0)
+        return LBM_EINVAL;
+    const int nbub = slab_rows > 0 ? 0 : nb;
+    h->n_bubbles = nbub;
+    for (int k = 0; k < nbub; ++k) h->bubbles[k] = b[k];
+    InstDev &d = h->desc;
+    d.cur = 0;
+    d.step = 0;
+    d.n_chunk = 0;
+    d.n_bubbles = nbub;
+    d.rho_l = rho_l;
+    d.rho_g = rho_g;
+    for (int k = 0; k < LBM_MAX_BUBBLES; ++k) {
+        d.bx[k] = k < nbub ? b[k].x0 : 0.0;
+        d.by[k] = k < nbub ? b[k].y0 : 0.0;
+    }
+    h->desc_dirty = true;
+    if (h->batch) h->batch->dirty = true;
+    TRY(sync_own(h));
+    hipStream_t st = stream_of(h);
+    TRYHIP(launch_reset_diag(h->d_desc, st));
+    TRYHIP(launch_init(h->p.precision, h->d_desc, slab_rows, b, nbub, rho_l, rho_g, W, delta,
+                       noise_amp, seed, (long long)h->p.nx * h->p.ny, st));
+    h->has_state = true;
+    h->sticky = LBM_OK;
+    return LBM_OK;
+}
+
+int lbm_step(void *handle, int64_t n)
+{
+    Instance *h = (Instance *)handle;
+    if (!h || n < 0) return LBM_EINVAL;
+    if (h->batch) return LBM_ESTATE;
+    if (!h->has_state) return LBM_ESTATE;
+    if (h->sticky != LBM_OK) return h->sticky;
+    TRY(sync_own(h));
+    while (n > 0) {
+        const int K = (int)std::min<int64_t>(n, MAX_CHUNK);
+        if (h->desc.n_chunk != K) {
+            h->desc.n_chunk = K;
+            h->desc_dirty = true;
+        }
+        TRY(sync_own(h));
+        TRY(run_chunk(h->graphs, h->p.precision, h->variant, h->d_desc, 1, h->d_tiles, h->ntiles, K,
+                      h->stream));
+        advance_mirror(h->desc, K);   // the device advanced its own copy
+        n -= K;
+    }
+    return LBM_OK;
+}
+
+int lbm_step_timed(void *handle, int64_t n, float *ms)
+{
+    Instance *h = (Instance *)handle;
+    if (!h || n < 0 || !ms) return LBM_EINVAL;
+    if (h->batch) return LBM_ESTATE;
+    if (!h->has_state) return LBM_ESTATE;
+    if (h->sticky != LBM_OK) return h->sticky;
+    // a one-member batch view of the instance, on the instance's stream
+    Batch tmp;
+    tmp.precision = h->p.precision;
+    tmp.stream = h->stream;
+    tmp.max_inst = 1;
+    tmp.max_tiles = h->L.max_tiles;
+    tmp.d_descs = h->d_desc;
+    tmp.d_tiles = h->d_tiles;
+    tmp.members.push_back(h);
+    tmp.variant = h->variant;
+    if (tmp.stager_desc.init(sizeof(InstDev)) != LBM_OK || tmp.stager_tiles.init(sizeof(Tile) * h->L.max_tiles) != LBM_OK) {
+        tmp.stager_desc.release();
+        tmp.stager_tiles.release();
+        return LBM_EHIP;
+    }
+    h->batch = &tmp;
+    int rc = batch_run(&tmp, std::vector<int64_t>(1, n), true, ms);
+    h->batch = nullptr;
+    (void)hipStreamSynchronize(h->stream);
+    tmp.stager_desc.release();
+    tmp.stager_tiles.release();
+    h->tiles_dirty = true;
+    h->desc_dirty = true;
+    return rc;
+}
+
+int lbm_sync(void *handle)
+{
+    Instance *h = (Instance *)handle;
+    if (!h) return LBM_EINVAL;
+    TRYHIP(hipStreamSynchronize(stream_of(h)));
+    return read_latch(h);
+}
+
+int lbm_macros(void *handle, void *d_rho, void *d_ux, void *d_uy, void *d_p, lbm_diag *out)
+{
+    Instance *h = (Instance *)handle;
+    if (!h) return LBM_EINVAL;
+    if (!h->has_state) return LBM_ESTATE;
+    TRY(sync_own(h));
+    hipStream_t st = stream_of(h);
+    TRYHIP(launch_psi_pass(h->p.precision, h->variant, h->d_desc, h->d_tiles, h->ntiles, -1, st));
+    TRYHIP(launch_macros(h->p.precision, h->variant, h->d_desc, h->d_tiles, h->ntiles, d_rho, d_ux, d_uy,
+                         (double *)d_p, st));
+    TRYHIP(launch_reduce(h->d_desc, h->ntiles, st));
+    double res[N_PARTIAL];
+    unsigned long long run[2];
+    int flag = 0;
+    TRYHIP(hipMemcpyAsync(res, h->desc.result, sizeof(res), hipMemcpyDeviceToHost, st));
+    TRYHIP(hipMemcpyAsync(run, h->desc.wall_run, sizeof(run), hipMemcpyDeviceToHost, st));
+    TRYHIP(hipMemcpyAsync(&flag, h->desc.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    TRYHIP(hipStreamSynchronize(st));
+    if (flag) h->sticky = LBM_ENONFINITE;
+    if (out) {
+        memset(out, 0, sizeof(*out));
+        out->step = h->desc.step;
+        out->mass = res[0];
+        out->mom_x = res[1];
+        out->mom_y = res[2];
+        out->n_bubbles = h->n_bubbles;
+        out->nonfinite = flag ? 1 : 0;
+        for (int k = 0; k < LBM_MAX_BUBBLES; ++k) {
+            out->gas_area[k] = k < h->n_bubbles ? res[3 + k] : 0.0;
+            out->radius[k] = k < h->n_bubbles ? sqrt(res[3 + k] / M_PI) : 0.0;
+        }
+        if (h->p.walls_y && run[0] != 0ull) {
+            const unsigned long long u = (run[0] >> 63) ? (run[0] & 0x7fffffffffffffffull) : ~run[0];
+            double v;
+            memcpy(&v, &u, sizeof v);
+            out->wall_p_max = v;
+            out->wall_p_step = (int64_t)run[1];
+        } else {
+            out->wall_p_max = -INFINITY;
+            out->wall_p_step = -1;
+        }
+    }
+    return h->sticky;
+}
+
+int lbm_get_populations(void *handle, void *d_out)
+{
+    Instance *h = (Instance *)handle;
+    if (!h || !d_out) return LBM_EINVAL;
+    if (!h->has_state) return LBM_ESTATE;
+    TRY(sync_own(h));
+    TRYHIP(launch_pack(h->p.precision, h->d_desc, h->p.nx, h->p.ny, d_out, 1, stream_of(h)));
+    return LBM_OK;
+}
+
+int lbm_set_populations(void *handle, const void *d_in)
+{
+    Instance *h = (Instance *)handle;
+    if (!h || !d_in) return LBM_EINVAL;
+    h->desc.cur = 0;
+    h->desc.step = 0;
+    h->desc.n_chunk = 0;
+    h->desc_dirty = true;
+    if (h->batch) h->batch->dirty = true;
+    TRY(sync_own(h));
+    hipStream_t st = stream_of(h);
+    TRYHIP(launch_reset_diag(h->d_desc, st));
+    TRYHIP(launch_pack(h->p.precision, h->d_desc, h->p.nx, h->p.ny, const_cast<void *>(d_in), 0, st));
+    h->has_state = true;
+    h->sticky = LBM_OK;
+    return LBM_OK;
+}
+
+// ---- checkpoints ------------------------------------------------------------
+struct CkptHeader {
+    uint64_t magic;
+    lbm_params p;
+    int64_t step;
+    int32_t n_bubbles, pad;
+    lbm_bubble bubbles[LBM_MAX_BUBBLES];
+    double rho_l, rho_g;
+    unsigned long long wall_run[2];
+};
+
+int lbm_checkpoint_bytes(void *handle, size_t *bytes)
+{
+    Instance *h = (Instance *)handle;
+    if (!h || !bytes) return LBM_EINVAL;
+    *bytes = sizeof(CkptHeader) + 9 * (size_t)h->p.nx * h->p.ny * elem_size(h->p.precision);
+    return LBM_OK;
+}
+
+int lbm_save(void *handle, void *host_buf, size_t bytes)
+{
+    Instance *h = (Instance *)handle;
+    size_t need = 0;
+    TRY(lbm_checkpoint_bytes(handle, &need));
+    if (!host_buf) return LBM_EINVAL;
+    if (bytes < need) return LBM_ENOMEM;
+    if (!h->has_state) return LBM_ESTATE;
+    TRY(sync_own(h));
+    hipStream_t st = stream_of(h);
+    TRYHIP(hipStreamSynchronize(st));
+    CkptHeader hd;
+    memset(&hd, 0, sizeof hd);
+    hd.magic = CKPT_MAGIC;
+    hd.p = h->p;
+    hd.step = h->desc.step;
+    hd.n_bubbles = h->n_bubbles;
+    for (int k = 0; k < h->n_bubbles; ++k) hd.bubbles[k] = h->bubbles[k];
+    hd.rho_l = h->desc.rho_l;
+    hd.rho_g = h->desc.rho_g;
+    TRYHIP(hipMemcpy(hd.wall_run, h->desc.wall_run, sizeof hd.wall_run, hipMemcpyDeviceToHost));
+    memcpy(host_buf, &hd, sizeof hd);
+    const size_t es = elem_size(h->p.precision);
+    char *dst = (char *)host_buf + sizeof hd;
+    const char *src = (const char *)h->desc.f[h->desc.cur];
+    for (int a = 0; a < 9; ++a)
+        TRYHIP(hipMemcpy2D(dst + (size_t)a * h->p.nx * h->p.ny * es, h->p.nx * es,
+                           src + (size_t)a * h->desc.plane * es, h->L.pitch * es, h->p.nx * es,
+                           h->p.ny, hipMemcpyDeviceToHost));
+    return LBM_OK;
+}
+
+int lbm_load(void *handle, const void *host_buf, size_t bytes)
+{
+    Instance *h = (Instance *)handle;
+    size_t need = 0;
+    TRY(lbm_checkpoint_bytes(handle, &need));
+    if (!host_buf) return LBM_EINVAL;
+    if (bytes < need) return LBM_ENOMEM;
+    CkptHeader hd;
+    memcpy(&hd, host_buf, sizeof hd);
+    if (hd.magic != CKPT_MAGIC || memcmp(&hd.p, &h->p, sizeof(lbm_params)) != 0) return LBM_EINVAL;
+    hipStream_t st = stream_of(h);
+    TRYHIP(hipStreamSynchronize(st));
+    InstDev &d = h->desc;
+    d.cur = 0;
+    d.step = hd.step;
+    d.n_chunk = 0;
+    h->n_bubbles = hd.n_bubbles;
+    d.n_bubbles = hd.n_bubbles;
+    d.rho_l = hd.rho_l;
+    d.rho_g = hd.rho_g;
+    for (int k = 0; k < LBM_MAX_BUBBLES; ++k) {
+        h->bubbles[k] = hd.bubbles[k];
+        d.bx[k] = k < hd.n_bubbles ? hd.bubbles[k].x0 : 0.0;
+        d.by[k] = k < hd.n_bubbles ? hd.bubbles[k].y0 : 0.0;
+    }
+    h->desc_dirty = true;
+    if (h->batch) h->batch->dirty = true;
+    TRY(sync_own(h));
+    TRYHIP(launch_reset_diag(h->d_desc, st));
+    TRYHIP(hipStreamSynchronize(st));
+    TRYHIP(hipMemcpy(d.wall_run, hd.wall_run, sizeof hd.wall_run, hipMemcpyHostToDevice));
+    const size_t es = elem_size(h->p.precision);
+    const char *src = (const char *)host_buf + sizeof hd;
+    char *dst = (char *)d.f[0];
+    for (int a = 0; a < 9; ++a)
+        TRYHIP(hipMemcpy2D(dst + (size_t)a * d.plane * es, h->L.pitch * es,
+                           src + (size_t)a * h->p.nx * h->p.ny * es, h->p.nx * es, h->p.nx * es,
+                           h->p.ny, hipMemcpyHostToDevice));
+    h->has_state = true;
+    h->sticky = LBM_OK;
+    return LBM_OK;
+}
+
+// ---- variants ---------------------------------------------------------------
+int lbm_variant_count(void) { return kNumVariants; }
+
+const char *lbm_variant_name(int variant)
+{
+    if (variant < 0 || variant >= kNumVariants) return "";
+    return kVariants[variant].name;
+}
+
+int lbm_set_variant(void *handle, int variant)
+{
+    Instance *h = (Instance *)handle;
+    if (!h || variant < 0 || variant >= kNumVariants) return LBM_EINVAL;
+    if (h->variant != variant) {
+        h->variant = variant;
+        h->tiles_dirty = true;
+    }
+    return LBM_OK;
+}
+
+// ---- batch ------------------------------------------------------------------
+int lbm_batch_workspace_bytes(int max_instances, int64_t max_tiles, size_t *bytes)
+{
+    if (max_instances < 1 || max_tiles < 1 || !bytes) return LBM_EINVAL;
+    *bytes = round_up(sizeof(InstDev) * (size_t)max_instances, ALIGN) +
+             round_up(sizeof(Tile) * (size_t)max_tiles, ALIGN);
+    return LBM_OK;
+}
+
+int lbm_batch_create(int precision, int max_instances, int64_t max_tiles, void *d_workspace,
+                     size_t ws_bytes, void *hip_stream, void **batch)
+{
+    if (precision < LBM_FP64 || precision > LBM_FP32_MIXED || !batch || !d_workspace) return LBM_EINVAL;
+    if ((uintptr_t)d_workspace % ALIGN) return LBM_EINVAL;
+    size_t need = 0;
+    TRY(lbm_batch_workspace_bytes(max_instances, max_tiles, &need));
+    if (ws_bytes < need) return LBM_ENOMEM;
+    Batch *b = new Batch();
+    b->precision = precision;
+    b->stream = (hipStream_t)hip_stream;
+    b->max_inst = max_instances;
+    b->max_tiles = max_tiles;
+    b->d_descs = (InstDev *)d_workspace;
+    b->d_tiles = (Tile *)((char *)d_workspace + round_up(sizeof(InstDev) * (size_t)max_instances, ALIGN));
+    if (b->stager_desc.init(sizeof(InstDev) * (size_t)max_instances) != LBM_OK ||
+        b->stager_tiles.init(sizeof(Tile) * (size_t)max_tiles) != LBM_OK) {
+        b->stager_desc.release();
+        b->stager_tiles.release();
+        delete b;
+        return LBM_EHIP;
+    }
+    *batch = b;
+    return LBM_OK;
+}
+
+int lbm_batch_attach(void *batch, void *handle)
+{
+    Batch *b = (Batch *)batch;
+    Instance *h = (Instance *)handle;
+    if (!b || !h) return LBM_EINVAL;
+    if (h->batch) return LBM_ESTATE;
+    if (h->p.precision != b->precision) return LBM_EINVAL;
+    if ((int)b->members.size() >= b->max_inst) return LBM_ENOMEM;
+    // order the instance's pending work before the batch's
+    TRYHIP(hipStreamSynchronize(h->stream));
+    h->batch = b;
+    b->members.push_back(h);
+    b->dirty = true;
+    return LBM_OK;
+}
+
+int lbm_batch_detach(void *batch, void *handle)
+{
+    Batch *b = (Batch *)batch;
+    Instance *h = (Instance *)handle;
+    if (!b || !h || h->batch != b) return LBM_EINVAL;
+    TRYHIP(hipStreamSynchronize(b->stream));
+    auto it = std::find(b->members.begin(), b->members.end(), h);
+    if (it != b->members.end()) b->members.erase(it);
+    h->batch = nullptr;
+    h->desc_dirty = true;
+    b->dirty = true;
+    return LBM_OK;
+}
+
+int lbm_batch_size(void *batch, int *n_attached)
+{
+    Batch *b = (Batch *)batch;
+    if (!b || !n_attached) return LBM_EINVAL;
+    *n_attached = (int)b->members.size();
+    return LBM_OK;
+}
+
+int lbm_batch_step(void *batch, int64_t n)
+{
+    Batch *b = (Batch *)batch;
+    if (!b || n < 0) return LBM_EINVAL;
+    return batch_run(b, std::vector<int64_t>(b->members.size(), n), false, nullptr);
+}
+
+int lbm_batch_step_each(void *batch, const int64_t *counts, int n_counts)
+{
+    Batch *b = (Batch *)batch;
+    if (!b || (n_counts > 0 && !counts) || n_counts != (int)b->members.size()) return LBM_EINVAL;
+    std::vector<int64_t> c(counts, counts + n_counts);
+    for (int64_t v : c)
+        if (v < 0) return LBM_EINVAL;
+    return batch_run(b, c, false, nullptr);
+}
+
+int lbm_batch_step_timed(void *batch, int64_t n, float *ms)
+{
+    Batch *b = (Batch *)batch;
+    if (!b || n < 0 || !ms) return LBM_EINVAL;
+    return batch_run(b, std::vector<int64_t>(b->members.size(), n), true, ms);
+}
+
+int lbm_batch_set_variant(void *batch, int variant)
+{
+    Batch *b = (Batch *)batch;
+    if (!b || variant < 0 || variant >= kNumVariants) return LBM_EINVAL;
+    if (b->variant != variant) {
+        b->variant = variant;
+        b->dirty = true;
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_autotune(void *batch, int reps, int *best_variant, float *ms_per_step)
+{
+    Batch *b = (Batch *)batch;
+    if (!b || reps < 1 || !best_variant) return LBM_EINVAL;
+    if (b->members.empty()) return LBM_ESTATE;
+    hipEvent_t e0, e1;
+    TRYHIP(hipEventCreate(&e0));
+    TRYHIP(hipEventCreate(&e1));
+    int best = b->variant;
+    float best_ms = INFINITY;
+    int rc = LBM_OK;
+    for (int v = 0; v < kNumVariants && rc == LBM_OK; ++v) {
+        rc = lbm_batch_set_variant(b, v);
+        if (rc == LBM_OK) rc = lbm_batch_step(b, std::min(reps, 8));     // warm-up and capture
+        if (rc == LBM_OK) rc = hip_ok(hipEventRecord(e0, b->stream));
+        if (rc == LBM_OK) rc = lbm_batch_step(b, reps);
+        if (rc == LBM_OK) rc = hip_ok(hipEventRecord(e1, b->stream));
+        if (rc == LBM_OK) rc = hip_ok(hipEventSynchronize(e1));
+        float t = 0.f;
+        if (rc == LBM_OK) rc = hip_ok(hipEventElapsedTime(&t, e0, e1));
+        if (rc == LBM_OK && t < best_ms) {
+            best_ms = t;
+            best = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != LBM_OK) return rc;
+    TRY(lbm_batch_set_variant(b, best));
+    *best_variant = best;
+    if (ms_per_step) *ms_per_step = best_ms / reps;
+    return LBM_OK;
+}
+
+void lbm_batch_destroy(void *batch)
+{
+    Batch *b = (Batch *)batch;
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    for (Instance *h : b->members) {
+        h->batch = nullptr;
+        h->desc_dirty = true;
+    }
+    drop_graphs(b->graphs);
+    b->stager_desc.release();
+    b->stager_tiles.release();
+    delete b;
+}
+
+int lbm_copy_kernel(void *d_dst, const void *d_src, size_t n, void *hip_stream)
+{
+    if (!d_dst || !d_src || n % 16) return LBM_EINVAL;
+    TRYHIP(launch_copy(d_dst, d_src, n, (hipStream_t)hip_stream));
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+// Internal declarations shared by the liblbm translation units: the device
+// descriptor of an instance, the tile work-list entry, the workspace layout
+// and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm.h"
+
+namespace lbm {
+
+// Columns of a tile: one 64-wide wavefront spans a tile row.
+constexpr int TILE_X = 64;
+// Threads per block: 4 wavefronts, one per row group of a tile.
+constexpr int BLOCK = 256;
+constexpr int ROW_GROUPS = BLOCK / TILE_X;
+// Longest chunk of steps replayed from one captured graph; also the number of
+// per-step wall-pressure slots an instance keeps.
+constexpr int MAX_CHUNK = 256;
+// Binary64 partial sums per tile written by the diagnostics kernel:
+// mass, momentum x, momentum y, then one gas area per bubble.
+constexpr int N_PARTIAL = 3 + LBM_MAX_BUBBLES;
+
+// Device-visible description of one instance.  The host keeps a mirror and
+// uploads it when it changes; kernels only read it, except the end-of-chunk
+// kernel, which folds the per-step wall-pressure slots.
+struct InstDev {
+    void *f[2];                    // population buffers, 9 planes of ny*pitch
+    void *psi;                     // ny*pitch pseudopotential values
+    double *partials;              // N_PARTIAL * max_tiles binary64 partial sums
+    int *flag;                     // [0] non-finite latch
+    unsigned long long *wall_keys; // MAX_CHUNK per-step keys of the wall-row max of p
+    unsigned long long *wall_run;  // [0] running max key, [1] its step
+    double *result;                // reduced diagnostics (N_PARTIAL + 2 values)
+    long long plane;               // ny * pitch
+    long long step;                // steps taken before the current chunk
+    int nx, ny, pitch, walls;
+    int cur;                       // index of the buffer holding the current state
+    int n_chunk;                   // steps this instance takes in the current chunk
+    int tiles_x;                   // tiles per tile row for the current variant
+    int n_bubbles;
+    // Eq. 15 and Eq. 13 constants
+    double a, b4, RT, G;
+    // relaxation rates of Eq. 2 that act on non-conserved moments
+    double s_e, s_z, s_q, s_nu;
+    // Li's term after (I - Lambda/2): s_e * 0.75 eps and s_zeta * 0.75 eps
+    double li_e, li_z;
+    double rho_l, rho_g;           // gas-fraction densities
+    double bx[LBM_MAX_BUBBLES], by[LBM_MAX_BUBBLES];
+};
+
+// One entry of the tile work-list.
+struct Tile {
+    int inst;
+    int x0, y0;
+    int tile_index;                // index of the tile within its instance
+};
+
+// Tile-shape variants: a tile is TILE_X columns by ROW_GROUPS * rows_per_thread
+// rows.
+struct Variant {
+    int rows_per_thread;
+    const char *name;
+};
+extern const Variant kVariants[];
+extern const int kNumVariants;
+
+inline int tile_rows(int variant) { return ROW_GROUPS * kVariants[variant].rows_per_thread; }
+
+// Kernels, launched on a stream.  prec is an lbm_precision.
+hipError_t launch_psi_pass(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles,
+                           int ntiles, int s, hipStream_t st);
+hipError_t launch_collide_stream(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles,
+                                 int ntiles, int s, hipStream_t st);
+hipError_t launch_chunk_end(const InstDev *d_inst, int ninst, hipStream_t st);
+hipError_t launch_init(int prec, const InstDev *d_inst, int slab_rows, const lbm_bubble *b, int nb,
+                       double rho_l, double rho_g, double W, double delta, double noise_amp,
+                       uint64_t seed, long long nsites, hipStream_t st);
+hipError_t launch_macros(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles,
+                         int ntiles, void *rho, void *ux, void *uy, double *p, hipStream_t st);
+hipError_t launch_reduce(const InstDev *d_inst, int ntiles, hipStream_t st);
+hipError_t launch_pack(int prec, const InstDev *d_inst, int nx, int ny, void *dense, int to_dense,
+                       hipStream_t st);
+hipError_t launch_reset_diag(const InstDev *d_inst, hipStream_t st);
+hipError_t launch_copy(void *dst, const void *src, size_t n, hipStream_t st);
+
+}  // namespace lbm

@@ -1,0 +1,724 @@
+// gfx950 kernels of the D2Q9 pseudopotential MRT lattice Boltzmann timestep
+// (Shan et al., arXiv:1605.01800).
+//
+// Populations are kept post-streaming in structure-of-arrays form: plane a
+// holds f_a for every site, rows of `pitch` elements (a multiple of 64), so a
+// 64-wide wavefront reads one row segment of one plane with one coalesced
+// access.  A step is two passes over a work-list of 64 x (4*RY) tiles:
+//
+//   psi pass               rho = sum_a f_a, p (Eq. 15), psi (Eq. 13); stores psi
+//   force+collide+stream   stages the tile's psi plus a one-site halo in LDS,
+//                          then per site: F (Eq. 7), v (Eq. 6), moments and
+//                          equilibria (Eq. 4), Li's source (Eq. 14), relaxation
+//                          (Eq. 3), f* = M^-1 m*, and pushes f*_a to x + e_a in
+//                          the other buffer (Eq. 5) or, through a wall, back to
+//                          the same site as the opposite population.
+//
+// The moment transform is applied per site with its integer structure written
+// out (it is a sparse 9x9 map, not a contraction, so it stays on the vector
+// ALUs).  Blocks are mapped to tiles so that each of the eight XCDs works on a
+// contiguous run of tiles, which keeps halo re-reads in that XCD's L2.
+#include <math.h>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+
+const Variant kVariants[] = {{1, "64x4"}, {2, "64x8"}, {4, "64x16"}, {8, "64x32"}};
+const int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+namespace {
+
+constexpr int NXCD = 8;
+
+// Block b of a grid of nblocks (a multiple of NXCD) runs tile xcd_tile(b):
+// consecutive dispatch slots of one XCD take consecutive tiles.
+__device__ __forceinline__ int xcd_tile(int b, int nblocks)
+{
+    const int per = nblocks / NXCD;
+    return (b % NXCD) * per + b / NXCD;
+}
+
+// Source buffer of step s of the current chunk; s < 0 means the current state.
+__device__ __forceinline__ int src_buffer(const InstDev &d, int s)
+{
+    return s < 0 ? d.cur : ((d.cur + s) & 1);
+}
+
+// Carnahan-Starling pressure, Eq. 15, with eta = (b/4) rho.
+template <typename T>
+__device__ __forceinline__ T eos_pressure(T rho, T RT, T a, T b4)
+{
+    const T eta = b4 * rho;
+    const T om = T(1) - eta;
+    const T num = T(1) + eta * (T(1) + eta * (T(1) - eta));
+    return rho * RT * num / (om * om * om) - a * rho * rho;
+}
+
+// Pseudopotential, Eq. 13 with c = 1 and c_s^2 = 1/3.  EOS64 evaluates the
+// pressure and the root in binary64 whatever T is.
+template <typename T, bool EOS64>
+__device__ __forceinline__ T pseudopotential(T rho, const InstDev &d)
+{
+    if (EOS64) {
+        const double r = (double)rho;
+        const double p = eos_pressure<double>(r, d.RT, d.a, d.b4);
+        return (T)sqrt(2.0 * (p - r * (1.0 / 3.0)) / d.G);
+    } else {
+        const T p = eos_pressure<T>(rho, (T)d.RT, (T)d.a, (T)d.b4);
+        return sqrt(T(2) * (p - rho * T(1.0 / 3.0)) / (T)d.G);
+    }
+}
+
+// Order-preserving map of a binary64 value onto an unsigned 64-bit key.
+__device__ __forceinline__ unsigned long long order_key(double v)
+{
+    unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
+template <typename T>
+__device__ __forceinline__ bool finite_value(T v)
+{
+    return isfinite(v);
+}
+
+// ---------------------------------------------------------------------------
+// psi pass
+// ---------------------------------------------------------------------------
+template <typename T, bool EOS64, int RY>
+__global__ __launch_bounds__(BLOCK) void psi_pass_kernel(const InstDev *__restrict__ insts,
+                                                         const Tile *__restrict__ tiles, int ntiles,
+                                                         int s)
+{
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    if (t >= ntiles) return;
+    const Tile tl = tiles[t];
+    const InstDev &d = insts[tl.inst];
+    if (s >= d.n_chunk) return;
+    const T *__restrict__ f = (const T *)d.f[src_buffer(d, s)];
+    T *__restrict__ psi = (T *)d.psi;
+    const long long P = d.plane;
+    const int lx = threadIdx.x & (TILE_X - 1);
+    const int g = threadIdx.x / TILE_X;
+    const int x = tl.x0 + lx;
+    const bool track = s >= 0 && d.walls && (tl.y0 == 0 || tl.y0 + ROW_GROUPS * RY >= d.ny);
+    bool bad = false;
+    double wmax = -INFINITY;
+
+    T rho[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int y = tl.y0 + g * RY + r;
+        rho[r] = T(0);
+        if (x < d.nx && y < d.ny) {
+            const long long i = (long long)y * d.pitch + x;
+            T v[9];
+#pragma unroll
+            for (int a = 0; a < 9; ++a) v[a] = f[a * P + i];
+            rho[r] = (((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]))) + v[8];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int y = tl.y0 + g * RY + r;
+        if (x < d.nx && y < d.ny) {
+            const long long i = (long long)y * d.pitch + x;
+            const T ps = pseudopotential<T, EOS64>(rho[r], d);
+            psi[i] = ps;
+            bad |= !finite_value(ps);
+            if (track && (y == 0 || y == d.ny - 1))
+                wmax = fmax(wmax, eos_pressure<double>((double)rho[r], d.RT, d.a, d.b4));
+        }
+    }
+    if (bad) d.flag[0] = 1;
+    if (track) {
+        __shared__ double red[BLOCK];
+        red[threadIdx.x] = wmax;
+        __syncthreads();
+        for (int w = BLOCK / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0 && red[0] > -INFINITY)
+            atomicMax(&d.wall_keys[s], order_key(red[0]));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// collision of one site (Eqs. 6, 4, 14, 3 and f* = M^-1 m*)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Rates {
+    T s_e, s_z, s_q, s_nu;        // rates of the relaxed moments
+    T h_e, h_z, h_q, h_nu;        // 1 - s/2
+    T li_e, li_z;                 // s_e 0.75 eps, s_zeta 0.75 eps
+};
+
+template <typename T>
+__device__ __forceinline__ Rates<T> load_rates(const InstDev &d)
+{
+    Rates<T> r;
+    r.s_e = (T)d.s_e; r.s_z = (T)d.s_z; r.s_q = (T)d.s_q; r.s_nu = (T)d.s_nu;
+    r.h_e = (T)(1.0 - 0.5 * d.s_e); r.h_z = (T)(1.0 - 0.5 * d.s_z);
+    r.h_q = (T)(1.0 - 0.5 * d.s_q); r.h_nu = (T)(1.0 - 0.5 * d.s_nu);
+    r.li_e = (T)d.li_e; r.li_z = (T)d.li_z;
+    return r;
+}
+
+// f: post-streaming populations of the site (in), post-collision (out).
+// psi_c: psi at the site; Fx, Fy: force of Eq. 7.
+template <typename T>
+__device__ __forceinline__ void collide_site(T f[9], T psi_c, T Fx, T Fy, const Rates<T> &R)
+{
+    const T rho = (((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7]))) + f[8];
+    const T jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    const T jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    const T inv_rho = T(1) / rho;
+    // Eq. 6 with delta_t = 1
+    const T vx = (jx + T(0.5) * Fx) * inv_rho;
+    const T vy = (jy + T(0.5) * Fy) * inv_rho;
+    const T v2 = vx * vx + vy * vy;
+
+    // non-conserved moments m = M f
+    const T axis = (f[1] + f[2]) + (f[3] + f[4]);
+    const T diag = (f[5] + f[6]) + (f[7] + f[8]);
+    const T m1 = T(-4) * f[0] - axis + T(2) * diag;
+    const T m2 = T(4) * f[0] - T(2) * axis + diag;
+    const T m4 = T(2) * (f[3] - f[1]) + (f[5] - f[6]) + (f[8] - f[7]);
+    const T m6 = T(2) * (f[4] - f[2]) + (f[5] + f[6]) - (f[7] + f[8]);
+    const T m7 = (f[1] - f[2]) + (f[3] - f[4]);
+    const T m8 = (f[5] - f[6]) + (f[7] - f[8]);
+
+    // equilibria, Eq. 4
+    const T e1 = rho * (T(-2) + T(3) * v2);
+    const T e2 = rho * (T(1) - T(3) * v2);
+    const T e4 = -rho * vx;
+    const T e6 = -rho * vy;
+    const T e7 = rho * (vx * vx - vy * vy);
+    const T e8 = rho * vx * vy;
+
+    // (I - Lambda/2) S with S of Eq. 14; for the e and zeta rows
+    // (1 - s/2) / (tau - 1/2) = s, so Li's term enters as s 0.75 eps |F|^2 / psi^2.
+    const T vF = vx * Fx + vy * Fy;
+    const T li = (Fx * Fx + Fy * Fy) / (psi_c * psi_c);
+    const T q1 = R.h_e * T(6) * vF + R.li_e * li;
+    const T q2 = -R.h_z * T(6) * vF - R.li_z * li;
+    const T q4 = -R.h_q * Fx;
+    const T q6 = -R.h_q * Fy;
+    const T q7 = R.h_nu * T(2) * (vx * Fx - vy * Fy);
+    const T q8 = R.h_nu * (vx * Fy + vy * Fx);
+
+    // relaxation, Eq. 3.  rho and j are collision invariants up to the
+    // source: m0* = rho, m3* = jx + Fx, m5* = jy + Fy for any s_rho, s_j.
+    const T n1 = m1 - R.s_e * (m1 - e1) + q1;
+    const T n2 = m2 - R.s_z * (m2 - e2) + q2;
+    const T n4 = m4 - R.s_q * (m4 - e4) + q4;
+    const T n6 = m6 - R.s_q * (m6 - e6) + q6;
+    const T n7 = m7 - R.s_nu * (m7 - e7) + q7;
+    const T n8 = m8 - R.s_nu * (m8 - e8) + q8;
+
+    // f* = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m*.
+    // The conserved moments are divided, not multiplied by a rounded
+    // reciprocal: sum_a f*_a = 9 a0 and sum_a e_a f*_a = 6 (a3, a5), so a
+    // reciprocal rounded low (or high) would shrink (or grow) the total mass
+    // and momentum by the same relative amount at every step, a drift of
+    // 5.5e-17 (binary64) or 7.5e-9 (binary32) per step.  A correctly rounded
+    // quotient has no such bias.  The other moments relax, so a bias there
+    // does not accumulate.
+    const T a0 = rho / T(9);
+    const T a1 = n1 * T(1.0 / 36.0);
+    const T a2 = n2 * T(1.0 / 36.0);
+    const T a3 = (jx + Fx) / T(6);
+    const T a4 = n4 * T(1.0 / 12.0);
+    const T a5 = (jy + Fy) / T(6);
+    const T a6 = n6 * T(1.0 / 12.0);
+    const T a7 = n7 * T(0.25);
+    const T a8 = n8 * T(0.25);
+
+    const T ax = a0 - a1 - T(2) * a2;       // common part of the axis populations
+    const T dg = a0 + T(2) * a1 + a2;       // common part of the diagonals
+    const T px = a3 - T(2) * a4;
+    const T py = a5 - T(2) * a6;
+    const T qx = a3 + a4;
+    const T qy = a5 + a6;
+    f[0] = a0 - T(4) * a1 + T(4) * a2;
+    f[1] = ax + px + a7;
+    f[2] = ax + py - a7;
+    f[3] = ax - px + a7;
+    f[4] = ax - py - a7;
+    f[5] = dg + qx + qy + a8;
+    f[6] = dg - qx + qy - a8;
+    f[7] = dg - qx - qy + a8;
+    f[8] = dg + qx - qy - a8;
+}
+
+// ---------------------------------------------------------------------------
+// force + collide + stream pass
+// ---------------------------------------------------------------------------
+template <typename T, int RY>
+__global__ __launch_bounds__(BLOCK) void collide_stream_kernel(const InstDev *__restrict__ insts,
+                                                               const Tile *__restrict__ tiles,
+                                                               int ntiles, int s)
+{
+    constexpr int TY = ROW_GROUPS * RY;
+    constexpr int LW = TILE_X + 2;
+    __shared__ T sp[(TY + 2) * LW];
+
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    if (t >= ntiles) return;
+    const Tile tl = tiles[t];
+    const InstDev &d = insts[tl.inst];
+    if (s >= d.n_chunk) return;
+    const int sb = src_buffer(d, s);
+    const T *__restrict__ f = (const T *)d.f[sb];
+    T *__restrict__ fo = (T *)d.f[sb ^ 1];
+    const T *__restrict__ psi = (const T *)d.psi;
+    const long long P = d.plane;
+    const int nx = d.nx, ny = d.ny, pitch = d.pitch;
+
+    // psi of the tile and a one-site ring; x wraps, y wraps or mirrors at walls
+    for (int k = threadIdx.x; k < (TY + 2) * LW; k += BLOCK) {
+        const int ly = k / LW;
+        const int lxx = k - ly * LW;
+        int gx = (tl.x0 - 1 + lxx) % nx;
+        if (gx < 0) gx += nx;
+        int gy = tl.y0 - 1 + ly;
+        if (d.walls) {
+            gy = gy < 0 ? 0 : (gy > ny - 1 ? ny - 1 : gy);
+        } else {
+            gy %= ny;
+            if (gy < 0) gy += ny;
+        }
+        sp[k] = psi[(long long)gy * pitch + gx];
+    }
+    __syncthreads();
+
+    const Rates<T> R = load_rates<T>(d);
+    const int lx = threadIdx.x & (TILE_X - 1);
+    const int g = threadIdx.x / TILE_X;
+    const int x = tl.x0 + lx;
+    if (x >= nx) return;
+    const int xe = (x + 1 == nx) ? 0 : x + 1;
+    const int xw = (x == 0) ? nx - 1 : x - 1;
+
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int ly = g * RY + r;
+        const int y = tl.y0 + ly;
+        if (y >= ny) break;
+        const long long rc = (long long)y * pitch;
+        T v[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) v[a] = f[a * P + rc + x];
+
+        // Eq. 7 with the weights 1/3 (axes) and 1/12 (diagonals)
+        const T *c = sp + (ly + 1) * LW + (lx + 1);
+        const T pc = c[0];
+        const T pE = c[1], pW = c[-1], pN = c[LW], pS = c[-LW];
+        const T pNE = c[LW + 1], pNW = c[LW - 1], pSW = c[-LW - 1], pSE = c[-LW + 1];
+        const T gx = T(1.0 / 3.0) * (pE - pW) + T(1.0 / 12.0) * ((pNE - pNW) + (pSE - pSW));
+        const T gy = T(1.0 / 3.0) * (pN - pS) + T(1.0 / 12.0) * ((pNE + pNW) - (pSE + pSW));
+        const T mG = -(T)d.G;
+        const T Fx = mG * pc * gx;
+        const T Fy = mG * pc * gy;
+
+        collide_site<T>(v, pc, Fx, Fy, R);
+
+        // Eq. 5: push f*_a to x + e_a; through a wall it returns as f_opp(a)
+        const bool top = (y == ny - 1), bot = (y == 0);
+        int yn = y + 1, ys = y - 1;
+        if (!d.walls) {
+            if (top) yn = 0;
+            if (bot) ys = ny - 1;
+        }
+        const long long rn = (long long)yn * pitch, rs = (long long)ys * pitch;
+        fo[0 * P + rc + x] = v[0];
+        fo[1 * P + rc + xe] = v[1];
+        fo[3 * P + rc + xw] = v[3];
+        if (d.walls && top) {
+            fo[4 * P + rc + x] = v[2];
+            fo[7 * P + rc + x] = v[5];
+            fo[8 * P + rc + x] = v[6];
+        } else {
+            fo[2 * P + rn + x] = v[2];
+            fo[5 * P + rn + xe] = v[5];
+            fo[6 * P + rn + xw] = v[6];
+        }
+        if (d.walls && bot) {
+            fo[2 * P + rc + x] = v[4];
+            fo[5 * P + rc + x] = v[7];
+            fo[6 * P + rc + x] = v[8];
+        } else {
+            fo[4 * P + rs + x] = v[4];
+            fo[7 * P + rs + xw] = v[7];
+            fo[8 * P + rs + xe] = v[8];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// end of a chunk: fold the per-step wall maxima, advance step counter/parity
+// ---------------------------------------------------------------------------
+__global__ void chunk_end_kernel(InstDev *insts, int ninst)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ninst) return;
+    InstDev &d = insts[k];
+    const int n = d.n_chunk;
+    if (n <= 0) return;
+    if (d.walls) {
+        unsigned long long best = d.wall_run[0];
+        long long best_step = (long long)d.wall_run[1];
+        for (int j = 0; j < n; ++j) {
+            const unsigned long long key = d.wall_keys[j];
+            if (key > best) {
+                best = key;
+                best_step = d.step + j;
+            }
+            d.wall_keys[j] = 0ull;
+        }
+        d.wall_run[0] = best;
+        d.wall_run[1] = (unsigned long long)best_step;
+    }
+    d.step += n;
+    d.cur ^= (n & 1);
+}
+
+// Clears the latch and the wall-pressure record of one instance.
+__global__ void reset_diag_kernel(const InstDev *inst)
+{
+    const InstDev &d = *inst;
+    for (int j = threadIdx.x; j < MAX_CHUNK; j += blockDim.x) d.wall_keys[j] = 0ull;
+    if (threadIdx.x == 0) {
+        d.wall_run[0] = 0ull;
+        d.wall_run[1] = 0ull;
+        d.flag[0] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// initial state (Eq. 16), f_a = w_a rho
+// ---------------------------------------------------------------------------
+struct InitArgs {
+    int slab_rows, nb;
+    double rho_l, rho_g, W, delta, noise_amp;
+    unsigned long long seed;
+    double bx[LBM_MAX_BUBBLES], by[LBM_MAX_BUBBLES], br[LBM_MAX_BUBBLES];
+};
+
+// SplitMix64 (Steele, Lea and Flood): one output for the state s.
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long s)
+{
+    unsigned long long z = s + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <typename T>
+__global__ void init_kernel(const InstDev *inst, InitArgs A)
+{
+    const InstDev &d = *inst;
+    const long long n = (long long)d.nx * d.ny;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int y = (int)(i / d.nx);
+    const int x = (int)(i - (long long)y * d.nx);
+    const double rl = A.rho_l * (1.0 + A.delta);
+    double dist;                                // positive on the liquid side
+    if (A.slab_rows > 0) {
+        dist = 0.5 * A.slab_rows - fabs(y - 0.5 * (d.ny - 1));
+    } else {
+        dist = INFINITY;
+        for (int k = 0; k < A.nb; ++k) {
+            const double dx = x - A.bx[k], dy = y - A.by[k];
+            dist = fmin(dist, sqrt(dx * dx + dy * dy) - A.br[k]);
+        }
+    }
+    double rho = 0.5 * (rl + A.rho_g) + 0.5 * (rl - A.rho_g) * tanh(2.0 * dist / A.W);
+    if (A.noise_amp != 0.0) {
+        const double u = (double)(splitmix64(A.seed ^ (unsigned long long)i) >> 11) *
+                         (1.0 / 9007199254740992.0);
+        rho *= 1.0 + A.noise_amp * (2.0 * u - 1.0);
+    }
+    T *f = (T *)d.f[d.cur];
+    const long long j = (long long)y * d.pitch + x;
+    const double w0 = 4.0 / 9.0, w1 = 1.0 / 9.0, w5 = 1.0 / 36.0;
+    f[j] = (T)(w0 * rho);
+#pragma unroll
+    for (int a = 1; a <= 4; ++a) f[a * d.plane + j] = (T)(w1 * rho);
+#pragma unroll
+    for (int a = 5; a <= 8; ++a) f[a * d.plane + j] = (T)(w5 * rho);
+}
+
+// ---------------------------------------------------------------------------
+// macroscopic fields and per-tile binary64 partial sums
+// ---------------------------------------------------------------------------
+template <typename T, int RY>
+__global__ __launch_bounds__(BLOCK) void macros_kernel(const InstDev *__restrict__ insts,
+                                                       const Tile *__restrict__ tiles, int ntiles,
+                                                       T *rho_out, T *ux_out, T *uy_out,
+                                                       double *p_out)
+{
+    const int t = blockIdx.x;
+    if (t >= ntiles) return;
+    const Tile tl = tiles[t];
+    const InstDev &d = insts[tl.inst];
+    const T *__restrict__ f = (const T *)d.f[d.cur];
+    const T *__restrict__ psi = (const T *)d.psi;
+    const long long P = d.plane;
+    const int nx = d.nx, ny = d.ny, pitch = d.pitch;
+    const int lx = threadIdx.x & (TILE_X - 1);
+    const int g = threadIdx.x / TILE_X;
+    const int x = tl.x0 + lx;
+
+    double acc[N_PARTIAL];
+#pragma unroll
+    for (int q = 0; q < N_PARTIAL; ++q) acc[q] = 0.0;
+
+    for (int r = 0; r < RY; ++r) {
+        const int y = tl.y0 + g * RY + r;
+        if (x >= nx || y >= ny) continue;
+        const long long i = (long long)y * pitch + x;
+        T v[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) v[a] = f[a * P + i];
+        const T rho = (((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]))) + v[8];
+        const T jx = (v[1] - v[3]) + (v[5] - v[6]) + (v[8] - v[7]);
+        const T jy = (v[2] - v[4]) + (v[5] + v[6]) - (v[7] + v[8]);
+        auto ps = [&](int dx, int dy) -> T {
+            int xx = x + dx;
+            xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+            int yy = y + dy;
+            if (d.walls) yy = yy < 0 ? 0 : (yy > ny - 1 ? ny - 1 : yy);
+            else yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+            return psi[(long long)yy * pitch + xx];
+        };
+        const T pc = ps(0, 0);
+        const T gx = T(1.0 / 3.0) * (ps(1, 0) - ps(-1, 0)) +
+                     T(1.0 / 12.0) * ((ps(1, 1) - ps(-1, 1)) + (ps(1, -1) - ps(-1, -1)));
+        const T gy = T(1.0 / 3.0) * (ps(0, 1) - ps(0, -1)) +
+                     T(1.0 / 12.0) * ((ps(1, 1) + ps(-1, 1)) - (ps(1, -1) + ps(-1, -1)));
+        const T mG = -(T)d.G;
+        const T Fx = mG * pc * gx, Fy = mG * pc * gy;
+        const T mx = jx + T(0.5) * Fx, my = jy + T(0.5) * Fy;
+        const long long o = (long long)y * nx + x;
+        if (rho_out) rho_out[o] = rho;
+        if (ux_out) ux_out[o] = mx / rho;
+        if (uy_out) uy_out[o] = my / rho;
+        if (p_out) p_out[o] = eos_pressure<double>((double)rho, d.RT, d.a, d.b4);
+        acc[0] += (double)rho;
+        acc[1] += (double)mx;
+        acc[2] += (double)my;
+        if (d.n_bubbles > 0) {
+            double frac = (d.rho_l - (double)rho) / (d.rho_l - d.rho_g);
+            frac = frac < 0.0 ? 0.0 : (frac > 1.0 ? 1.0 : frac);
+            int best = 0;
+            double bd = INFINITY;
+            for (int k = 0; k < d.n_bubbles; ++k) {
+                const double dx = x - d.bx[k], dy = y - d.by[k];
+                const double dd = dx * dx + dy * dy;
+                if (dd < bd) { bd = dd; best = k; }
+            }
+#pragma unroll
+            for (int k = 0; k < LBM_MAX_BUBBLES; ++k)
+                if (k == best) acc[3 + k] += frac;
+        }
+    }
+    __shared__ double red[BLOCK];
+    for (int q = 0; q < N_PARTIAL; ++q) {
+        red[threadIdx.x] = acc[q];
+        __syncthreads();
+        for (int w = BLOCK / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) d.partials[(long long)q * ntiles + tl.tile_index] = red[0];
+        __syncthreads();
+    }
+}
+
+// Sums the per-tile partials of one instance in a fixed order.
+__global__ void reduce_kernel(const InstDev *inst, int ntiles)
+{
+    const InstDev &d = *inst;
+    __shared__ double red[BLOCK];
+    for (int q = 0; q < N_PARTIAL; ++q) {
+        double acc = 0.0;
+        for (int k = threadIdx.x; k < ntiles; k += BLOCK) acc += d.partials[(long long)q * ntiles + k];
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int w = BLOCK / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) d.result[q] = red[0];
+        __syncthreads();
+    }
+}
+
+// Copies between the padded state buffer and a dense f[a][y][x] array.
+template <typename T>
+__global__ void pack_kernel(const InstDev *inst, T *dense, int to_dense)
+{
+    const InstDev &d = *inst;
+    const long long n = (long long)d.nx * d.ny;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int a = blockIdx.y;
+    if (i >= n) return;
+    const int y = (int)(i / d.nx);
+    const int x = (int)(i - (long long)y * d.nx);
+    T *f = (T *)d.f[d.cur];
+    const long long j = a * d.plane + (long long)y * d.pitch + x;
+    if (to_dense) dense[a * n + i] = f[j];
+    else f[j] = dense[a * n + i];
+}
+
+__global__ void copy_kernel(uint4 *__restrict__ dst, const uint4 *__restrict__ src, size_t n16)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+inline unsigned grid_for(int ntiles)
+{
+    return (unsigned)(((ntiles + NXCD - 1) / NXCD) * NXCD);
+}
+
+template <typename T, bool E64>
+hipError_t psi_dispatch(int variant, const InstDev *di, const Tile *dt, int nt, int s, hipStream_t st)
+{
+    const dim3 grid(grid_for(nt)), block(BLOCK);
+    switch (kVariants[variant].rows_per_thread) {
+    case 1: psi_pass_kernel<T, E64, 1><<<grid, block, 0, st>>>(di, dt, nt, s); break;
+    case 2: psi_pass_kernel<T, E64, 2><<<grid, block, 0, st>>>(di, dt, nt, s); break;
+    case 4: psi_pass_kernel<T, E64, 4><<<grid, block, 0, st>>>(di, dt, nt, s); break;
+    case 8: psi_pass_kernel<T, E64, 8><<<grid, block, 0, st>>>(di, dt, nt, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t collide_dispatch(int variant, const InstDev *di, const Tile *dt, int nt, int s,
+                            hipStream_t st)
+{
+    const dim3 grid(grid_for(nt)), block(BLOCK);
+    switch (kVariants[variant].rows_per_thread) {
+    case 1: collide_stream_kernel<T, 1><<<grid, block, 0, st>>>(di, dt, nt, s); break;
+    case 2: collide_stream_kernel<T, 2><<<grid, block, 0, st>>>(di, dt, nt, s); break;
+    case 4: collide_stream_kernel<T, 4><<<grid, block, 0, st>>>(di, dt, nt, s); break;
+    case 8: collide_stream_kernel<T, 8><<<grid, block, 0, st>>>(di, dt, nt, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t macros_dispatch(int variant, const InstDev *di, const Tile *dt, int nt, void *rho,
+                           void *ux, void *uy, double *p, hipStream_t st)
+{
+    const dim3 grid(nt), block(BLOCK);
+    T *r = (T *)rho, *u = (T *)ux, *v = (T *)uy;
+    switch (kVariants[variant].rows_per_thread) {
+    case 1: macros_kernel<T, 1><<<grid, block, 0, st>>>(di, dt, nt, r, u, v, p); break;
+    case 2: macros_kernel<T, 2><<<grid, block, 0, st>>>(di, dt, nt, r, u, v, p); break;
+    case 4: macros_kernel<T, 4><<<grid, block, 0, st>>>(di, dt, nt, r, u, v, p); break;
+    case 8: macros_kernel<T, 8><<<grid, block, 0, st>>>(di, dt, nt, r, u, v, p); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_psi_pass(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles,
+                           int ntiles, int s, hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    if (prec == LBM_FP64) return psi_dispatch<double, false>(variant, d_inst, d_tiles, ntiles, s, st);
+    if (prec == LBM_FP32) return psi_dispatch<float, false>(variant, d_inst, d_tiles, ntiles, s, st);
+    return psi_dispatch<float, true>(variant, d_inst, d_tiles, ntiles, s, st);
+}
+
+hipError_t launch_collide_stream(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles,
+                                 int ntiles, int s, hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    if (prec == LBM_FP64) return collide_dispatch<double>(variant, d_inst, d_tiles, ntiles, s, st);
+    return collide_dispatch<float>(variant, d_inst, d_tiles, ntiles, s, st);
+}
+
+hipError_t launch_chunk_end(const InstDev *d_inst, int ninst, hipStream_t st)
+{
+    if (ninst <= 0) return hipSuccess;
+    chunk_end_kernel<<<(ninst + 63) / 64, 64, 0, st>>>(const_cast<InstDev *>(d_inst), ninst);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_diag(const InstDev *d_inst, hipStream_t st)
+{
+    reset_diag_kernel<<<1, 256, 0, st>>>(d_inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(int prec, const InstDev *d_inst, int slab_rows, const lbm_bubble *b, int nb,
+                       double rho_l, double rho_g, double W, double delta, double noise_amp,
+                       uint64_t seed, long long nsites, hipStream_t st)
+{
+    InitArgs A;
+    A.slab_rows = slab_rows;
+    A.nb = nb;
+    A.rho_l = rho_l;
+    A.rho_g = rho_g;
+    A.W = W;
+    A.delta = delta;
+    A.noise_amp = noise_amp;
+    A.seed = seed;
+    for (int k = 0; k < LBM_MAX_BUBBLES; ++k) {
+        A.bx[k] = k < nb ? b[k].x0 : 0.0;
+        A.by[k] = k < nb ? b[k].y0 : 0.0;
+        A.br[k] = k < nb ? b[k].r0 : 0.0;
+    }
+    const unsigned grid = (unsigned)((nsites + 255) / 256);
+    if (prec == LBM_FP64) init_kernel<double><<<grid, 256, 0, st>>>(d_inst, A);
+    else init_kernel<float><<<grid, 256, 0, st>>>(d_inst, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_macros(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles,
+                         int ntiles, void *rho, void *ux, void *uy, double *p, hipStream_t st)
+{
+    if (prec == LBM_FP64) return macros_dispatch<double>(variant, d_inst, d_tiles, ntiles, rho, ux, uy, p, st);
+    return macros_dispatch<float>(variant, d_inst, d_tiles, ntiles, rho, ux, uy, p, st);
+}
+
+hipError_t launch_reduce(const InstDev *d_inst, int ntiles, hipStream_t st)
+{
+    reduce_kernel<<<1, BLOCK, 0, st>>>(d_inst, ntiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(int prec, const InstDev *d_inst, int nx, int ny, void *dense, int to_dense,
+                       hipStream_t st)
+{
+    const long long n = (long long)nx * ny;
+    const dim3 grid((unsigned)((n + 255) / 256), 9);
+    if (prec == LBM_FP64) pack_kernel<double><<<grid, 256, 0, st>>>(d_inst, (double *)dense, to_dense);
+    else pack_kernel<float><<<grid, 256, 0, st>>>(d_inst, (float *)dense, to_dense);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(void *dst, const void *src, size_t n, hipStream_t st)
+{
+    const size_t n16 = n / 16;
+    size_t blocks = (n16 + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks == 0) return hipSuccess;
+    copy_kernel<<<(unsigned)blocks, 256, 0, st>>>((uint4 *)dst, (const uint4 *)src, n16);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

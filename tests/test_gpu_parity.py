@@ -1,0 +1,242 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances: binary64 GPU path within 1e-12 relative (max norm) of the oracle;
+binary32 paths within 1e-4 on density fields and bubble radii.  Single steps
+from generic states are compared population by population."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import coexist, diagnostics, stepper as ostep
+from tests.helpers import oracle_params, rel_inf, to_device, to_oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+L = pytest.importorskip("paper_1605_01800_amd.lbm")
+from paper_1605_01800_amd import inputs  # noqa: E402
+
+TOL = {"fp64": 1e-12, "fp32": 1e-4, "fp32_mixed": 1e-4}
+STEP_TOL = {"fp64": 1e-14, "fp32": 2e-6, "fp32_mixed": 2e-6}
+
+
+def _bubble_rho(P, T, R, walls=False, W=4.0):
+    rg, rl, _ = coexist.maxwell(T)
+    c = (0.5 * (P.nx - 1), 0.5 * (P.ny - 1) if not walls else P.ny / 3.0)
+    return ostep.init_density(P, bubbles=[(c[0], c[1], R)], rho_l=rl, rho_g=rg, W=W), rg, rl
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_mixed"])
+@pytest.mark.parametrize("nx,ny,walls", [(100, 37, False), (100, 37, True), (64, 8, False),
+                                         (130, 5, True), (1, 6, False), (3, 1, True)])
+def test_single_step_from_random_state(prec, nx, ny, walls):
+    """One step from a generic state on ragged grids (x not a multiple of 64,
+    tiny and degenerate sizes, both boundary kinds)."""
+    print("case", prec, nx, ny, walls, flush=True)
+    T = coexist.temperature(0.7)
+    p = L.make_params(nx, ny, T=T, walls=walls, precision=prec, tau_nu=0.6)
+    P = oracle_params(p)
+    rho, _, _ = _bubble_rho(P, T, min(nx, ny) / 4.0 + 0.5, walls)
+    f0 = inputs.random_populations(rho, seed=nx * 1000 + ny, amp=0.3)
+    sim = L.Sim(p)
+    dt = sim.dtype
+    sim.set_populations(to_device(f0, dt))
+    start = to_oracle(sim.populations())          # the state as the device holds it
+    sim.step(1)
+    got = to_oracle(sim.populations())
+    want = start.copy()
+    assert ostep.step(P, want, 1) == 0
+    assert rel_inf(got, want) < STEP_TOL[prec]
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_variants_are_bitwise_identical(prec):
+    """Every tile shape gives the same bits (no halo race, no order change)."""
+    T = coexist.temperature(0.7)
+    p = L.make_params(150, 70, T=T, walls=True, precision=prec, tau_nu=0.8)
+    outs = []
+    for v in range(len(L.variant_names())):
+        sim = L.Sim(p)
+        sim.set_variant(v)
+        sim.init_bubble([(74.5, 30.0, 14.0)], W=4.0)
+        sim.step(40)
+        outs.append(sim.populations().cpu())
+        sim.close()
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+
+
+def test_config1_fp64_matches_oracle_over_10000_steps():
+    """64 x 64 periodic, FP64, T = 0.7 T_c, bubble R = 16 at the centre, W = 2,
+    tau_nu = 0.8 (nu = 0.1); rho field, mass and radius every 500 steps."""
+    T = coexist.temperature(0.7)
+    rg, rl, _ = coexist.maxwell(T)
+    p = L.make_params(64, 64, T=T, precision="fp64", tau_nu=0.8)
+    P = oracle_params(p)
+    bub = [(31.5, 31.5, 16.0)]
+    sim = L.Sim(p).init_bubble(bub, rho_l=rl, rho_g=rg, W=2.0)
+    f = ostep.init_populations(P, ostep.init_density(P, bubbles=bub, rho_l=rl, rho_g=rg, W=2.0))
+    worst = 0.0
+    for k in range(20):
+        sim.step(500)
+        assert ostep.step(P, f, 500) == 0
+        m = sim.macros()
+        rho_o = ostep.density(P, f)
+        err = rel_inf(m["rho"].cpu().numpy(), rho_o)
+        worst = max(worst, err)
+        assert err < TOL["fp64"], (k, err)
+        mass_o = diagnostics.neumaier_sum(rho_o)
+        assert abs(m["diag"]["mass"] - mass_o) / mass_o < 1e-13
+        r_o = diagnostics.bubble_radius(rho_o, rl, rg)
+        assert abs(m["diag"]["radius"][0] - r_o) / r_o < TOL["fp64"]
+        assert m["diag"]["step"] == 500 * (k + 1)
+    print("max rel err", worst)
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp32_mixed"])
+def test_config1_fp32_within_1e4(prec):
+    T = coexist.temperature(0.7)
+    rg, rl, _ = coexist.maxwell(T)
+    p = L.make_params(64, 64, T=T, precision=prec, tau_nu=0.8)
+    P = oracle_params(p)
+    bub = [(31.5, 31.5, 16.0)]
+    sim = L.Sim(p).init_bubble(bub, rho_l=rl, rho_g=rg, W=2.0)
+    f = ostep.init_populations(P, ostep.init_density(P, bubbles=bub, rho_l=rl, rho_g=rg, W=2.0))
+    for k in range(4):
+        sim.step(1000)
+        assert ostep.step(P, f, 1000) == 0
+        m = sim.macros()
+        rho_o = ostep.density(P, f)
+        assert rel_inf(m["rho"].cpu().numpy(), rho_o) < TOL[prec]
+        r_o = diagnostics.bubble_radius(rho_o, rl, rg)
+        assert abs(m["diag"]["radius"][0] - r_o) / r_o < TOL[prec]
+    sim.close()
+
+
+def test_walls_collapse_fp64_matches_oracle():
+    """Wall-bounded collapse set-up (Section 4.1): liquid at rho_l (1 + delta),
+    seeded noise, halfway bounce-back at both walls."""
+    T = coexist.temperature(0.6)
+    rg, rl, _ = coexist.maxwell(T)
+    p = L.make_params(96, 80, T=T, walls=True, precision="fp64", tau_nu=0.6)
+    P = oracle_params(p)
+    bub = [(47.5, 30.0, 18.0)]
+    kw = dict(rho_l=rl, rho_g=rg, W=5.0, delta=0.02, noise_amp=1e-3, seed=7)
+    sim = L.Sim(p).init_bubble(bub, **kw)
+    f = ostep.init_populations(P, ostep.init_density(P, bubbles=bub, **kw))
+    assert rel_inf(to_oracle(sim.populations()), f) < 1e-15
+    for _ in range(3):
+        sim.step(200)
+        assert ostep.step(P, f, 200) == 0
+        m = sim.macros()
+        assert rel_inf(m["rho"].cpu().numpy(), ostep.density(P, f)) < TOL["fp64"]
+    sim.close()
+
+
+def test_macros_match_oracle_fields():
+    T = coexist.temperature(0.8)
+    p = L.make_params(70, 50, T=T, walls=True, precision="fp64", tau_nu=0.6)
+    P = oracle_params(p)
+    sim = L.Sim(p).init_bubble([(34.5, 20.0, 10.0)], W=4.0)
+    sim.step(300)
+    m = sim.macros()
+    f = to_oracle(sim.populations())
+    rho, vx, vy, pr = ostep.macros(P, f)
+    assert rel_inf(m["rho"].cpu().numpy(), rho) < 1e-15
+    assert np.max(np.abs(m["ux"].cpu().numpy() - vx)) < 1e-15
+    assert np.max(np.abs(m["uy"].cpu().numpy() - vy)) < 1e-15
+    assert np.max(np.abs(m["p"].cpu().numpy() - pr)) < 1e-15
+    d = m["diag"]
+    assert abs(d["mom_x"] - np.sum(rho * vx)) < 1e-13
+    assert abs(d["mom_y"] - np.sum(rho * vy)) < 1e-13
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_equals_alone_bitwise(prec):
+    """Uneven grids stepped together give the bits of each stepped alone, also
+    with different step counts per instance."""
+    T6, T8 = coexist.temperature(0.6), coexist.temperature(0.8)
+    specs = [(L.make_params(64, 64, T=T8, precision=prec), [(31.5, 31.5, 12.0)]),
+             (L.make_params(200, 90, T=T6, walls=True, precision=prec, tau_nu=0.8), [(99.5, 30.0, 20.0)]),
+             (L.make_params(77, 129, T=T8, precision=prec, tau_nu=0.51), [(38.0, 64.0, 15.0)])]
+    counts = [300, 173, 256]
+    alone = []
+    for (p, b), n in zip(specs, counts):
+        s = L.Sim(p).init_bubble(b, W=5.0)
+        s.step(n)
+        alone.append(s.populations().cpu())
+        s.close()
+    batch = L.Batch(precision=prec, max_instances=4, max_tiles=4096)
+    sims = [L.Sim(p).init_bubble(b, W=5.0) for p, b in specs]
+    for s in sims:
+        batch.attach(s)
+    batch.step_each(counts)
+    batch.sync()
+    for s, a, n in zip(sims, alone, counts):
+        assert s.diag()["step"] == n
+        assert torch.equal(s.populations().cpu(), a)
+    batch.close()
+
+
+def test_checkpoint_roundtrip_is_bitwise():
+    T = coexist.temperature(0.7)
+    p = L.make_params(90, 60, T=T, walls=True, precision="fp32", tau_nu=0.6)
+    a = L.Sim(p).init_bubble([(44.5, 25.0, 12.0)], W=5.0, delta=0.01)
+    a.step(123)
+    img = a.save()
+    a.step(200)
+    ref = a.populations().cpu()
+    b = L.Sim(p).load(img)
+    assert b.diag()["step"] == 123
+    b.step(200)
+    assert torch.equal(b.populations().cpu(), ref)
+    a.close()
+    b.close()
+
+
+def test_nonfinite_state_latches_and_refuses_to_step():
+    """A density next to the EOS pole makes psi^2 < 0 (Eq. 13): the step
+    latches the error, the next sync reports it, further steps are refused."""
+    T = coexist.temperature(0.7)
+    p = L.make_params(32, 16, T=T, precision="fp64")
+    rho = np.full((16, 32), 0.2)
+    rho[5, 7] = 0.99
+    f = inputs.random_populations(rho, 0, amp=0.0)
+    sim = L.Sim(p)
+    sim.set_populations(to_device(f, sim.dtype))
+    sim.step(1)
+    with pytest.raises(L.NonFiniteError):
+        sim.sync()
+    with pytest.raises(L.NonFiniteError):
+        sim.step(1)
+    sim.init_bubble([(15.5, 7.5, 4.0)], W=3.0)      # a fresh state clears the latch
+    sim.step(5)
+    sim.sync()
+    sim.close()
+
+
+def test_wall_pressure_peak_matches_oracle():
+    T = coexist.temperature(0.6)
+    rg, rl, _ = coexist.maxwell(T)
+    p = L.make_params(80, 48, T=T, walls=True, precision="fp64", tau_nu=0.6)
+    P = oracle_params(p)
+    bub = [(39.5, 14.0, 9.0)]
+    kw = dict(rho_l=rl, rho_g=rg, W=4.0, delta=0.03)
+    sim = L.Sim(p).init_bubble(bub, **kw)
+    f = ostep.init_populations(P, ostep.init_density(P, bubbles=bub, **kw))
+    best, best_step = -math.inf, -1
+    for t in range(300):
+        rho = ostep.density(P, f)
+        pw = max(np.max(ostep.eos_pressure(P, rho[0])), np.max(ostep.eos_pressure(P, rho[-1])))
+        if pw > best:
+            best, best_step = pw, t
+        ostep.step(P, f, 1)
+    sim.step(300)
+    d = sim.diag()
+    assert d["wall_p_step"] == best_step
+    assert abs(d["wall_p_max"] - best) <= 1e-12 * abs(best)
+    sim.close()
