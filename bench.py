@@ -28,6 +28,8 @@ HBM_PEAK_GBS = 8000.0
 # read psi, write 9 f), by element size
 BYTES_PSI = {4: 9 * 4 + 4, 8: 9 * 8 + 8}
 BYTES_COLLIDE = {4: 9 * 4 + 4 + 9 * 4, 8: 9 * 8 + 8 + 9 * 8}
+# the fused kernel reads the nine populations and writes nine (psi stays in LDS)
+BYTES_FUSED = {4: 18 * 4, 8: 18 * 8}
 
 
 def parse():
@@ -41,7 +43,30 @@ def parse():
     ap.add_argument("--no-fp64-plain", action="store_true")
     ap.add_argument("--variant", type=int, default=-1, help="tile variant; -1 autotunes")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run liblbm's plain copy kernel over MIB MiB, 5 times, and exit "
+                         "(reference for the memory-traffic counters)")
     return ap.parse_args()
+
+
+def calibrate_copy(mib):
+    import torch
+    from paper_1605_01800_amd import lbm as L
+    n = mib << 20
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    L.copy_kernel(dst, src, n, st)
+    e0.record(st)
+    for _ in range(5):
+        L.copy_kernel(dst, src, n, st)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    assert torch.equal(dst, src)
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "ms": ms,
+                      "GB_s": 2 * n / (ms * 1e-3) / 1e9}), flush=True)
 
 
 def laplace_sweep_sims(L, precision, device):
@@ -116,6 +141,9 @@ def fp64_plain(L, device, steps):
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(got --gpus %d)" % args.gpus, file=sys.stderr)
@@ -168,16 +196,32 @@ def main():
     print("# timed %d steps: %.3f ms/step, %.0f MLUPS" % (args.steps, ms / args.steps, mlups),
           file=sys.stderr, flush=True)
 
-    # per-kernel device time: an event pair around every launch, on the batch's stream
+    # Dominant kernel.  Fused variants launch one kernel per step, so its average
+    # launch duration is the timed region over the step count (an upper bound:
+    # it includes the gaps between launches and one end-of-chunk kernel per 256
+    # steps).  Two-pass variants time each launch with its own event pair on the
+    # batch's stream.
+    vname = L.variant_names()[variant]
+    fused = vname.startswith("fused")
     nk = min(args.steps, 100)
     ms_psi, ms_col = batch.step_timed(nk)
-    t_psi, t_col = ms_psi / nk, ms_col / nk
-    bw_psi = BYTES_PSI[es] * sites / (t_psi * 1e-3) / 1e9
-    bw_col = BYTES_COLLIDE[es] * sites / (t_col * 1e-3) / 1e9
-    dominant = ("collide_stream", t_col, bw_col, BYTES_COLLIDE[es]) if t_col >= t_psi else \
-        ("psi_pass", t_psi, bw_psi, BYTES_PSI[es])
-    print("# psi pass %.4f ms (%.0f GB/s), collide %.4f ms (%.0f GB/s)" % (t_psi, bw_psi, t_col, bw_col),
-          file=sys.stderr, flush=True)
+    if fused:
+        t_dom = ms / args.steps
+        dominant = ("fused_kernel", t_dom, BYTES_FUSED[es])
+        kernels = {"fused_kernel": {"ms_region_avg": t_dom, "ms_event_pair_avg": ms_col / nk,
+                                    "bytes_per_site": BYTES_FUSED[es],
+                                    "GB_s": round(BYTES_FUSED[es] * sites / (t_dom * 1e-3) / 1e9, 1)}}
+    else:
+        t_psi, t_col = ms_psi / nk, ms_col / nk
+        dominant = ("collide_stream_kernel", t_col, BYTES_COLLIDE[es]) if t_col >= t_psi else \
+            ("psi_pass_kernel", t_psi, BYTES_PSI[es])
+        kernels = {"psi_pass_kernel": {"ms": t_psi, "bytes_per_site": BYTES_PSI[es],
+                                       "GB_s": round(BYTES_PSI[es] * sites / (t_psi * 1e-3) / 1e9, 1)},
+                   "collide_stream_kernel": {"ms": t_col, "bytes_per_site": BYTES_COLLIDE[es],
+                                             "GB_s": round(BYTES_COLLIDE[es] * sites / (t_col * 1e-3) / 1e9, 1)}}
+    achieved = dominant[2] * sites / (dominant[1] * 1e-3) / 1e9
+    print("# dominant %s %.4f ms/launch, %.0f GB/s of %d B/site" % (dominant[0], dominant[1], achieved,
+                                                                     dominant[2]), file=sys.stderr, flush=True)
 
     out = {
         "metric": "aggregate MLUPS + %HBM roofline (FP32 batched vs FP64 plain); p50/p99 latency",
@@ -196,19 +240,15 @@ def main():
         "roofline": {
             "bound": "hbm",
             "kernel": dominant[0],
-            "achieved": round(dominant[2], 1),
+            "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(dominant[2] / HBM_PEAK_GBS, 4),
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None,
-            "bytes_per_site": dominant[3],
+            "bytes_per_site": dominant[2],
             "launch_ms": dominant[1],
         },
-        "kernels": {
-            "psi_pass": {"ms": t_psi, "GB_s": round(bw_psi, 1), "bytes_per_site": BYTES_PSI[es]},
-            "collide_stream": {"ms": t_col, "GB_s": round(bw_col, 1), "bytes_per_site": BYTES_COLLIDE[es]},
-            "step_model_GB_s": round((BYTES_PSI[es] + BYTES_COLLIDE[es]) * sites / (ms / args.steps * 1e-3) / 1e9, 1),
-        },
+        "kernels": kernels,
     }
     batch.close()
     for s in sims:

@@ -133,6 +133,7 @@ struct Instance {
     InstDev *d_desc = nullptr;
     Tile *d_tiles = nullptr;
     int variant = 0;
+    int tiles_variant = -1;       // variant the device tile list was built for
     int ntiles = 0;
     bool tiles_dirty = true;
     bool desc_dirty = true;
@@ -222,13 +223,16 @@ int hip_ok(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EHIP; }
 
 hipStream_t stream_of(const Instance *h) { return h->batch ? h->batch->stream : h->stream; }
 
-// Makes the instance's own device descriptor and tile list current.
-int sync_own(Instance *h)
+// Makes the instance's own device descriptor current, and its tile list the
+// one of variant v (default: the instance's variant).
+int sync_own(Instance *h, int v = -1)
 {
     hipStream_t st = stream_of(h);
-    if (h->tiles_dirty) {
+    if (v < 0) v = h->variant;
+    if (h->tiles_dirty || h->tiles_variant != v) {
         std::vector<Tile> tl;
-        build_tiles(0, h->p, h->variant, tl);
+        build_tiles(0, h->p, v, tl);
+        h->tiles_variant = v;
         h->ntiles = (int)tl.size();
         h->desc.tiles_x = (h->p.nx + TILE_X - 1) / TILE_X;
         TRYHIP(hipMemcpyAsync(h->d_tiles, tl.data(), sizeof(Tile) * tl.size(), hipMemcpyHostToDevice, st));
@@ -249,8 +253,12 @@ int enqueue_chunk(int prec, int variant, const InstDev *d_inst, int ninst, const
                   int ntiles, int K, hipStream_t st)
 {
     for (int s = 0; s < K; ++s) {
-        TRYHIP(launch_psi_pass(prec, variant, d_inst, d_tiles, ntiles, s, st));
-        TRYHIP(launch_collide_stream(prec, variant, d_inst, d_tiles, ntiles, s, st));
+        if (kVariants[variant].fused) {
+            TRYHIP(launch_fused(prec, variant, d_inst, d_tiles, ntiles, s, st));
+        } else {
+            TRYHIP(launch_psi_pass(prec, variant, d_inst, d_tiles, ntiles, s, st));
+            TRYHIP(launch_collide_stream(prec, variant, d_inst, d_tiles, ntiles, s, st));
+        }
     }
     TRYHIP(launch_chunk_end(d_inst, ninst, st));
     return LBM_OK;
@@ -361,7 +369,17 @@ int batch_run(Batch *b, const std::vector<int64_t> &counts, bool timed, float *m
             rc = run_chunk(b->graphs, b->precision, b->variant, b->d_descs, n, b->d_tiles, b->ntiles, K,
                            b->stream);
         } else {
-            for (int s = 0; s < K && rc == LBM_OK; ++s) {
+            const bool fused = kVariants[b->variant].fused;
+            for (int s = 0; s < K && rc == LBM_OK && fused; ++s) {
+                float t;
+                rc = hip_ok(hipEventRecord(e0, b->stream));
+                if (rc == LBM_OK) rc = hip_ok(launch_fused(b->precision, b->variant, b->d_descs, b->d_tiles, b->ntiles, s, b->stream));
+                if (rc == LBM_OK) rc = hip_ok(hipEventRecord(e1, b->stream));
+                if (rc == LBM_OK) rc = hip_ok(hipEventSynchronize(e1));
+                if (rc == LBM_OK) rc = hip_ok(hipEventElapsedTime(&t, e0, e1));
+                if (rc == LBM_OK) ms[1] += t;
+            }
+            for (int s = 0; s < K && rc == LBM_OK && !fused; ++s) {
                 float t;
                 rc = hip_ok(hipEventRecord(e0, b->stream));
                 if (rc == LBM_OK) rc = hip_ok(launch_psi_pass(b->precision, b->variant, b->d_descs, b->d_tiles, b->ntiles, s, b->stream));
@@ -572,10 +590,11 @@ int lbm_macros(void *handle, void *d_rho, void *d_ux, void *d_uy, void *d_p, lbm
     Instance *h = (Instance *)handle;
     if (!h) return LBM_EINVAL;
     if (!h->has_state) return LBM_ESTATE;
-    TRY(sync_own(h));
+    // the diagnostics run the two-pass kernels over the 64x4 tiles
+    TRY(sync_own(h, 0));
     hipStream_t st = stream_of(h);
-    TRYHIP(launch_psi_pass(h->p.precision, h->variant, h->d_desc, h->d_tiles, h->ntiles, -1, st));
-    TRYHIP(launch_macros(h->p.precision, h->variant, h->d_desc, h->d_tiles, h->ntiles, d_rho, d_ux, d_uy,
+    TRYHIP(launch_psi_pass(h->p.precision, 0, h->d_desc, h->d_tiles, h->ntiles, -1, st));
+    TRYHIP(launch_macros(h->p.precision, 0, h->d_desc, h->d_tiles, h->ntiles, d_rho, d_ux, d_uy,
                          (double *)d_p, st));
     TRYHIP(launch_reduce(h->d_desc, h->ntiles, st));
     double res[N_PARTIAL];

@@ -57,22 +57,31 @@ struct Tile {
     int tile_index;                // index of the tile within its instance
 };
 
-// Tile-shape variants: a tile is TILE_X columns by ROW_GROUPS * rows_per_thread
-// rows.
+// Kernel variants.  Two-pass variants (fused == 0) launch the psi pass and the
+// force+collide+stream pass over tiles of TILE_X x (ROW_GROUPS * rows) sites,
+// each thread taking `rows` rows.  Fused variants (fused == 1) launch one
+// kernel per step over strips of TILE_X x rows sites that rebuild psi for the
+// strip and its one-site ring on the fly.
 struct Variant {
-    int rows_per_thread;
+    int fused;
+    int rows;
     const char *name;
 };
 extern const Variant kVariants[];
 extern const int kNumVariants;
 
-inline int tile_rows(int variant) { return ROW_GROUPS * kVariants[variant].rows_per_thread; }
+inline int tile_rows(int variant)
+{
+    return kVariants[variant].fused ? kVariants[variant].rows : ROW_GROUPS * kVariants[variant].rows;
+}
 
 // Kernels, launched on a stream.  prec is an lbm_precision.
 hipError_t launch_psi_pass(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles,
                            int ntiles, int s, hipStream_t st);
 hipError_t launch_collide_stream(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles,
                                  int ntiles, int s, hipStream_t st);
+hipError_t launch_fused(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles, int ntiles,
+                        int s, hipStream_t st);
 hipError_t launch_chunk_end(const InstDev *d_inst, int ninst, hipStream_t st);
 hipError_t launch_init(int prec, const InstDev *d_inst, int slab_rows, const lbm_bubble *b, int nb,
                        double rho_l, double rho_g, double W, double delta, double noise_amp,

@@ -24,7 +24,9 @@
 
 namespace lbm {
 
-const Variant kVariants[] = {{1, "64x4"}, {2, "64x8"}, {4, "64x16"}, {8, "64x32"}};
+const Variant kVariants[] = {
+    {0, 1, "2pass-64x4"},  {0, 2, "2pass-64x8"},  {0, 4, "2pass-64x16"}, {0, 8, "2pass-64x32"},
+    {1, 16, "fused-64x16"}, {1, 32, "fused-64x32"}, {1, 64, "fused-64x64"}, {1, 128, "fused-64x128"}};
 const int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 namespace {
@@ -43,6 +45,13 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks)
 __device__ __forceinline__ int src_buffer(const InstDev &d, int s)
 {
     return s < 0 ? d.cur : ((d.cur + s) & 1);
+}
+
+// rho = sum_a f_a, always in this order.
+template <typename T>
+__device__ __forceinline__ T density(const T v[9])
+{
+    return (((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]))) + v[8];
 }
 
 // Carnahan-Starling pressure, Eq. 15, with eta = (b/4) rho.
@@ -116,7 +125,7 @@ __global__ __launch_bounds__(BLOCK) void psi_pass_kernel(const InstDev *__restri
             T v[9];
 #pragma unroll
             for (int a = 0; a < 9; ++a) v[a] = f[a * P + i];
-            rho[r] = (((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]))) + v[8];
+            rho[r] = density<T>(v);
         }
     }
 #pragma unroll
@@ -253,6 +262,61 @@ __device__ __forceinline__ void collide_site(T f[9], T psi_c, T Fx, T Fy, const 
     f[8] = dg + qx - qy - a8;
 }
 
+// Eq. 7 at the site in column l of the centre row rC, with the rows below (rS)
+// and above (rN): F = -G psi(x) sum_a w_a psi(x + e_a) e_a, w = 1/3 on the
+// axes and 1/12 on the diagonals.
+template <typename T>
+__device__ __forceinline__ void interaction_force(const T *rS, const T *rC, const T *rN, int l, T mG,
+                                                  T &pc, T &Fx, T &Fy)
+{
+    pc = rC[l];
+    const T pE = rC[l + 1], pW = rC[l - 1], pN = rN[l], pS = rS[l];
+    const T pNE = rN[l + 1], pNW = rN[l - 1], pSW = rS[l - 1], pSE = rS[l + 1];
+    const T gx = T(1.0 / 3.0) * (pE - pW) + T(1.0 / 12.0) * ((pNE - pNW) + (pSE - pSW));
+    const T gy = T(1.0 / 3.0) * (pN - pS) + T(1.0 / 12.0) * ((pNE + pNW) - (pSE + pSW));
+    Fx = mG * pc * gx;
+    Fy = mG * pc * gy;
+}
+
+// Eq. 5: pushes the post-collision populations v of site (x, y) to x + e_a in
+// fo; x wraps (xe, xw are the wrapped east and west columns); in y the
+// neighbour wraps, or, through a wall, the population returns to (x, y) as
+// the opposite one (halfway bounce-back).
+template <typename T>
+__device__ __forceinline__ void push_store(T *__restrict__ fo, long long P, const T v[9], int x, int xe,
+                                           int xw, int y, int ny, int pitch, int walls)
+{
+    const bool top = (y == ny - 1), bot = (y == 0);
+    int yn = y + 1, ys = y - 1;
+    if (!walls) {
+        if (top) yn = 0;
+        if (bot) ys = ny - 1;
+    }
+    const long long rc = (long long)y * pitch;
+    const long long rn = (long long)yn * pitch, rs = (long long)ys * pitch;
+    fo[0 * P + rc + x] = v[0];
+    fo[1 * P + rc + xe] = v[1];
+    fo[3 * P + rc + xw] = v[3];
+    if (walls && top) {
+        fo[4 * P + rc + x] = v[2];
+        fo[7 * P + rc + x] = v[5];
+        fo[8 * P + rc + x] = v[6];
+    } else {
+        fo[2 * P + rn + x] = v[2];
+        fo[5 * P + rn + xe] = v[5];
+        fo[6 * P + rn + xw] = v[6];
+    }
+    if (walls && bot) {
+        fo[2 * P + rc + x] = v[4];
+        fo[5 * P + rc + x] = v[7];
+        fo[6 * P + rc + x] = v[8];
+    } else {
+        fo[4 * P + rs + x] = v[4];
+        fo[7 * P + rs + xw] = v[7];
+        fo[8 * P + rs + xe] = v[8];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // force + collide + stream pass
 // ---------------------------------------------------------------------------
@@ -312,48 +376,138 @@ __global__ __launch_bounds__(BLOCK) void collide_stream_kernel(const InstDev *__
 #pragma unroll
         for (int a = 0; a < 9; ++a) v[a] = f[a * P + rc + x];
 
-        // Eq. 7 with the weights 1/3 (axes) and 1/12 (diagonals)
-        const T *c = sp + (ly + 1) * LW + (lx + 1);
-        const T pc = c[0];
-        const T pE = c[1], pW = c[-1], pN = c[LW], pS = c[-LW];
-        const T pNE = c[LW + 1], pNW = c[LW - 1], pSW = c[-LW - 1], pSE = c[-LW + 1];
-        const T gx = T(1.0 / 3.0) * (pE - pW) + T(1.0 / 12.0) * ((pNE - pNW) + (pSE - pSW));
-        const T gy = T(1.0 / 3.0) * (pN - pS) + T(1.0 / 12.0) * ((pNE + pNW) - (pSE + pSW));
-        const T mG = -(T)d.G;
-        const T Fx = mG * pc * gx;
-        const T Fy = mG * pc * gy;
-
+        T pc, Fx, Fy;
+        interaction_force<T>(sp + ly * LW, sp + (ly + 1) * LW, sp + (ly + 2) * LW, lx + 1, -(T)d.G, pc,
+                             Fx, Fy);
         collide_site<T>(v, pc, Fx, Fy, R);
+        push_store<T>(fo, P, v, x, xe, xw, y, ny, pitch, d.walls);
+    }
+}
 
-        // Eq. 5: push f*_a to x + e_a; through a wall it returns as f_opp(a)
-        const bool top = (y == ny - 1), bot = (y == 0);
-        int yn = y + 1, ys = y - 1;
-        if (!d.walls) {
-            if (top) yn = 0;
-            if (bot) ys = ny - 1;
+// ---------------------------------------------------------------------------
+// fused pass: the whole step in one kernel
+// ---------------------------------------------------------------------------
+// A block owns a strip of TILE_X columns and H rows.  Its four wavefronts walk
+// down the strip together, wavefront w taking rows y0 - 1 + 4k + w at
+// iteration k: each loads the nine populations of its row (plus, in lanes 0
+// and 1, of the two columns left and right of the strip), forms rho and psi
+// (Eqs. 15, 13) and writes psi into a 16-row ring in LDS.  The row it loaded
+// two iterations earlier then has psi above and below it in the ring, and is
+// collided from the populations kept in registers (Eqs. 7, 6, 4, 14, 3) and
+// pushed to the other buffer (Eq. 5).  Every population is read from memory
+// once per step (the one-row and one-column rings are re-read by the
+// neighbouring strips), and psi never leaves LDS.
+//
+// Ring hazards: in iteration k the block writes psi of rows y0-1+4k .. y0+2+4k
+// and reads rows y0+4k-10 .. y0+4k-5, all written before the previous
+// barrier; the two sets are 4 to 12 rows apart, so with 16 slots no slot is
+// written while another wavefront reads it, and one barrier per iteration
+// suffices.
+template <typename T, bool EOS64, int H>
+__global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict__ insts,
+                                                      const Tile *__restrict__ tiles, int ntiles, int s)
+{
+    constexpr int RING = 16;
+    constexpr int LW = TILE_X + 2;
+    constexpr int NLOAD = (H + 2 + ROW_GROUPS - 1) / ROW_GROUPS;
+    constexpr int NK = NLOAD + 2;
+    static_assert(H % ROW_GROUPS == 0, "strip height must be a multiple of the row groups");
+    __shared__ T ring[RING * LW];
+
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    if (t >= ntiles) return;
+    const Tile tl = tiles[t];
+    const InstDev &d = insts[tl.inst];
+    if (s >= d.n_chunk) return;
+    const int sb = src_buffer(d, s);
+    const T *__restrict__ f = (const T *)d.f[sb];
+    T *__restrict__ fo = (T *)d.f[sb ^ 1];
+    const long long P = d.plane;
+    const int nx = d.nx, ny = d.ny, pitch = d.pitch, walls = d.walls;
+    const int lane = threadIdx.x & (TILE_X - 1);
+    const int w = threadIdx.x / TILE_X;
+    const int x = tl.x0 + lane;
+    const int xl = x < nx ? x : x % nx;                       // column this lane loads
+    const bool halo = lane < 2;                               // lanes that also load a ring column
+    const int xh = lane == 0 ? (tl.x0 == 0 ? nx - 1 : tl.x0 - 1) : (tl.x0 + TILE_X) % nx;
+    const int hslot = lane == 0 ? 0 : LW - 1;
+    const int xe = (x + 1 >= nx) ? 0 : x + 1;
+    const int xw = (x == 0) ? nx - 1 : x - 1;
+    const int y_end = min(tl.y0 + H, ny);                     // rows collided: [y0, y_end)
+    const bool track = walls && (tl.y0 == 0 || tl.y0 + H >= ny);
+    const Rates<T> R = load_rates<T>(d);
+    const T mG = -(T)d.G;
+
+    bool bad = false;
+    double wmax = -INFINITY;
+    T fa[9], fb[9];                                           // rows loaded 1 and 2 iterations ago
+#pragma unroll
+    for (int a = 0; a < 9; ++a) fa[a] = fb[a] = T(0);
+
+    for (int k = 0; k < NK; ++k) {
+        const int l = tl.y0 - 1 + ROW_GROUPS * k + w;         // row loaded now
+        const bool do_load = k < NLOAD && l <= tl.y0 + H && l <= ny;
+        int mr = l;                                           // memory row (ghost rows mirror or wrap)
+        if (walls) mr = mr < 0 ? 0 : (mr > ny - 1 ? ny - 1 : mr);
+        else mr = mr < 0 ? mr + ny : (mr >= ny ? mr - ny : mr);
+        T fn[9], fh[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) fn[a] = fh[a] = T(0);
+        if (do_load) {
+            const long long i = (long long)mr * pitch + xl;
+#pragma unroll
+            for (int a = 0; a < 9; ++a) fn[a] = f[a * P + i];
+            if (halo) {
+                const long long ih = (long long)mr * pitch + xh;
+#pragma unroll
+                for (int a = 0; a < 9; ++a) fh[a] = f[a * P + ih];
+            }
         }
-        const long long rn = (long long)yn * pitch, rs = (long long)ys * pitch;
-        fo[0 * P + rc + x] = v[0];
-        fo[1 * P + rc + xe] = v[1];
-        fo[3 * P + rc + xw] = v[3];
-        if (d.walls && top) {
-            fo[4 * P + rc + x] = v[2];
-            fo[7 * P + rc + x] = v[5];
-            fo[8 * P + rc + x] = v[6];
-        } else {
-            fo[2 * P + rn + x] = v[2];
-            fo[5 * P + rn + xe] = v[5];
-            fo[6 * P + rn + xw] = v[6];
+
+        // collide the row loaded two iterations ago
+        const int c = l - 2 * ROW_GROUPS;
+        if (k >= 2 && c >= tl.y0 && c < y_end && x < nx) {
+            const T *rS = ring + ((c - 1 + 2 * RING) % RING) * LW;
+            const T *rC = ring + ((c + 2 * RING) % RING) * LW;
+            const T *rN = ring + ((c + 1 + 2 * RING) % RING) * LW;
+            T pc, Fx, Fy;
+            interaction_force<T>(rS, rC, rN, lane + 1, mG, pc, Fx, Fy);
+            collide_site<T>(fb, pc, Fx, Fy, R);
+            push_store<T>(fo, P, fb, x, xe, xw, c, ny, pitch, walls);
         }
-        if (d.walls && bot) {
-            fo[2 * P + rc + x] = v[4];
-            fo[5 * P + rc + x] = v[7];
-            fo[6 * P + rc + x] = v[8];
-        } else {
-            fo[4 * P + rs + x] = v[4];
-            fo[7 * P + rs + xw] = v[7];
-            fo[8 * P + rs + xe] = v[8];
+
+        // psi of the row loaded now
+        if (do_load) {
+            T *row = ring + ((l + 2 * RING) % RING) * LW;
+            const T rho = density<T>(fn);
+            const T ps = pseudopotential<T, EOS64>(rho, d);
+            row[lane + 1] = ps;
+            bad |= !finite_value(ps);
+            if (halo) {
+                const T ph = pseudopotential<T, EOS64>(density<T>(fh), d);
+                row[hslot] = ph;
+                bad |= !finite_value(ph);
+            }
+            if (track && (l == 0 || l == ny - 1) && l >= tl.y0 && l < y_end && x < nx)
+                wmax = fmax(wmax, eos_pressure<double>((double)rho, d.RT, d.a, d.b4));
         }
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            fb[a] = fa[a];
+            fa[a] = fn[a];
+        }
+    }
+    if (bad) d.flag[0] = 1;
+    if (track) {
+        __shared__ double red[BLOCK];
+        red[threadIdx.x] = wmax;
+        __syncthreads();
+        for (int k2 = BLOCK / 2; k2 > 0; k2 >>= 1) {
+            if (threadIdx.x < k2) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + k2]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0 && red[0] > -INFINITY) atomicMax(&d.wall_keys[s], order_key(red[0]));
     }
 }
 
@@ -591,7 +745,7 @@ template <typename T, bool E64>
 hipError_t psi_dispatch(int variant, const InstDev *di, const Tile *dt, int nt, int s, hipStream_t st)
 {
     const dim3 grid(grid_for(nt)), block(BLOCK);
-    switch (kVariants[variant].rows_per_thread) {
+    switch (kVariants[variant].rows) {
     case 1: psi_pass_kernel<T, E64, 1><<<grid, block, 0, st>>>(di, dt, nt, s); break;
     case 2: psi_pass_kernel<T, E64, 2><<<grid, block, 0, st>>>(di, dt, nt, s); break;
     case 4: psi_pass_kernel<T, E64, 4><<<grid, block, 0, st>>>(di, dt, nt, s); break;
@@ -606,11 +760,25 @@ hipError_t collide_dispatch(int variant, const InstDev *di, const Tile *dt, int 
                             hipStream_t st)
 {
     const dim3 grid(grid_for(nt)), block(BLOCK);
-    switch (kVariants[variant].rows_per_thread) {
+    switch (kVariants[variant].rows) {
     case 1: collide_stream_kernel<T, 1><<<grid, block, 0, st>>>(di, dt, nt, s); break;
     case 2: collide_stream_kernel<T, 2><<<grid, block, 0, st>>>(di, dt, nt, s); break;
     case 4: collide_stream_kernel<T, 4><<<grid, block, 0, st>>>(di, dt, nt, s); break;
     case 8: collide_stream_kernel<T, 8><<<grid, block, 0, st>>>(di, dt, nt, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, bool E64>
+hipError_t fused_dispatch(int variant, const InstDev *di, const Tile *dt, int nt, int s, hipStream_t st)
+{
+    const dim3 grid(grid_for(nt)), block(BLOCK);
+    switch (kVariants[variant].rows) {
+    case 16: fused_kernel<T, E64, 16><<<grid, block, 0, st>>>(di, dt, nt, s); break;
+    case 32: fused_kernel<T, E64, 32><<<grid, block, 0, st>>>(di, dt, nt, s); break;
+    case 64: fused_kernel<T, E64, 64><<<grid, block, 0, st>>>(di, dt, nt, s); break;
+    case 128: fused_kernel<T, E64, 128><<<grid, block, 0, st>>>(di, dt, nt, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -622,7 +790,7 @@ hipError_t macros_dispatch(int variant, const InstDev *di, const Tile *dt, int n
 {
     const dim3 grid(nt), block(BLOCK);
     T *r = (T *)rho, *u = (T *)ux, *v = (T *)uy;
-    switch (kVariants[variant].rows_per_thread) {
+    switch (kVariants[variant].rows) {
     case 1: macros_kernel<T, 1><<<grid, block, 0, st>>>(di, dt, nt, r, u, v, p); break;
     case 2: macros_kernel<T, 2><<<grid, block, 0, st>>>(di, dt, nt, r, u, v, p); break;
     case 4: macros_kernel<T, 4><<<grid, block, 0, st>>>(di, dt, nt, r, u, v, p); break;
@@ -649,6 +817,16 @@ hipError_t launch_collide_stream(int prec, int variant, const InstDev *d_inst, c
     if (ntiles <= 0) return hipSuccess;
     if (prec == LBM_FP64) return collide_dispatch<double>(variant, d_inst, d_tiles, ntiles, s, st);
     return collide_dispatch<float>(variant, d_inst, d_tiles, ntiles, s, st);
+}
+
+hipError_t launch_fused(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles, int ntiles,
+                        int s, hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    if (!kVariants[variant].fused) return hipErrorInvalidValue;
+    if (prec == LBM_FP64) return fused_dispatch<double, false>(variant, d_inst, d_tiles, ntiles, s, st);
+    if (prec == LBM_FP32) return fused_dispatch<float, false>(variant, d_inst, d_tiles, ntiles, s, st);
+    return fused_dispatch<float, true>(variant, d_inst, d_tiles, ntiles, s, st);
 }
 
 hipError_t launch_chunk_end(const InstDev *d_inst, int ninst, hipStream_t st)

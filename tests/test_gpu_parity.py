@@ -27,19 +27,27 @@ def _bubble_rho(P, T, R, walls=False, W=4.0):
     return ostep.init_density(P, bubbles=[(c[0], c[1], R)], rho_l=rl, rho_g=rg, W=W), rg, rl
 
 
+def _variant(name):
+    return L.variant_names().index(name)
+
+
+@pytest.mark.parametrize("variant", ["2pass-64x4", "fused-64x16", "fused-64x128"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_mixed"])
 @pytest.mark.parametrize("nx,ny,walls", [(100, 37, False), (100, 37, True), (64, 8, False),
-                                         (130, 5, True), (1, 6, False), (3, 1, True)])
-def test_single_step_from_random_state(prec, nx, ny, walls):
+                                         (130, 5, True), (1, 6, False), (3, 1, True),
+                                         (200, 131, True)])
+def test_single_step_from_random_state(prec, nx, ny, walls, variant):
     """One step from a generic state on ragged grids (x not a multiple of 64,
-    tiny and degenerate sizes, both boundary kinds)."""
-    print("case", prec, nx, ny, walls, flush=True)
+    tiny and degenerate sizes, both boundary kinds), for the two-pass and the
+    fused kernels."""
+    print("case", prec, nx, ny, walls, variant, flush=True)
     T = coexist.temperature(0.7)
     p = L.make_params(nx, ny, T=T, walls=walls, precision=prec, tau_nu=0.6)
     P = oracle_params(p)
     rho, _, _ = _bubble_rho(P, T, min(nx, ny) / 4.0 + 0.5, walls)
     f0 = inputs.random_populations(rho, seed=nx * 1000 + ny, amp=0.3)
     sim = L.Sim(p)
+    sim.set_variant(_variant(variant))
     dt = sim.dtype
     sim.set_populations(to_device(f0, dt))
     start = to_oracle(sim.populations())          # the state as the device holds it
@@ -53,7 +61,8 @@ def test_single_step_from_random_state(prec, nx, ny, walls):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_variants_are_bitwise_identical(prec):
-    """Every tile shape gives the same bits (no halo race, no order change)."""
+    """Every tile shape, two-pass or fused, gives the same bits (no halo or
+    ring race, no change of arithmetic order)."""
     T = coexist.temperature(0.7)
     p = L.make_params(150, 70, T=T, walls=True, precision=prec, tau_nu=0.8)
     outs = []
@@ -116,7 +125,8 @@ def test_config1_fp32_within_1e4(prec):
     sim.close()
 
 
-def test_walls_collapse_fp64_matches_oracle():
+@pytest.mark.parametrize("variant", ["2pass-64x8", "fused-64x32"])
+def test_walls_collapse_fp64_matches_oracle(variant):
     """Wall-bounded collapse set-up (Section 4.1): liquid at rho_l (1 + delta),
     seeded noise, halfway bounce-back at both walls."""
     T = coexist.temperature(0.6)
@@ -125,7 +135,9 @@ def test_walls_collapse_fp64_matches_oracle():
     P = oracle_params(p)
     bub = [(47.5, 30.0, 18.0)]
     kw = dict(rho_l=rl, rho_g=rg, W=5.0, delta=0.02, noise_amp=1e-3, seed=7)
-    sim = L.Sim(p).init_bubble(bub, **kw)
+    sim = L.Sim(p)
+    sim.set_variant(_variant(variant))
+    sim.init_bubble(bub, **kw)
     f = ostep.init_populations(P, ostep.init_density(P, bubbles=bub, **kw))
     assert rel_inf(to_oracle(sim.populations()), f) < 1e-15
     for _ in range(3):
@@ -155,8 +167,9 @@ def test_macros_match_oracle_fields():
     sim.close()
 
 
+@pytest.mark.parametrize("variant", ["2pass-64x4", "fused-64x64"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_batch_equals_alone_bitwise(prec):
+def test_batch_equals_alone_bitwise(prec, variant):
     """Uneven grids stepped together give the bits of each stepped alone, also
     with different step counts per instance."""
     T6, T8 = coexist.temperature(0.6), coexist.temperature(0.8)
@@ -165,12 +178,16 @@ def test_batch_equals_alone_bitwise(prec):
              (L.make_params(77, 129, T=T8, precision=prec, tau_nu=0.51), [(38.0, 64.0, 15.0)])]
     counts = [300, 173, 256]
     alone = []
+    v = _variant(variant)
     for (p, b), n in zip(specs, counts):
-        s = L.Sim(p).init_bubble(b, W=5.0)
+        s = L.Sim(p)
+        s.set_variant(v)
+        s.init_bubble(b, W=5.0)
         s.step(n)
         alone.append(s.populations().cpu())
         s.close()
     batch = L.Batch(precision=prec, max_instances=4, max_tiles=4096)
+    batch.set_variant(v)
     sims = [L.Sim(p).init_bubble(b, W=5.0) for p, b in specs]
     for s in sims:
         batch.attach(s)
@@ -219,14 +236,17 @@ def test_nonfinite_state_latches_and_refuses_to_step():
     sim.close()
 
 
-def test_wall_pressure_peak_matches_oracle():
+@pytest.mark.parametrize("variant", ["2pass-64x4", "fused-64x16"])
+def test_wall_pressure_peak_matches_oracle(variant):
     T = coexist.temperature(0.6)
     rg, rl, _ = coexist.maxwell(T)
     p = L.make_params(80, 48, T=T, walls=True, precision="fp64", tau_nu=0.6)
     P = oracle_params(p)
     bub = [(39.5, 14.0, 9.0)]
     kw = dict(rho_l=rl, rho_g=rg, W=4.0, delta=0.03)
-    sim = L.Sim(p).init_bubble(bub, **kw)
+    sim = L.Sim(p)
+    sim.set_variant(_variant(variant))
+    sim.init_bubble(bub, **kw)
     f = ostep.init_populations(P, ostep.init_density(P, bubbles=bub, **kw))
     best, best_step = -math.inf, -1
     for t in range(300):
