@@ -68,6 +68,10 @@ int check_params(const lbm_params *p)
     if (p->precision < LBM_FP64 || p->precision > LBM_FP32_MIXED) return LBM_EINVAL;
     if (!(p->G < 0) || !(p->T > 0) || !(p->b > 0) || !(p->R > 0) || !(p->a >= 0)) return LBM_EINVAL;
     if (!isfinite(p->eps)) return LBM_EINVAL;
+    // kernels address a population plane with 32-bit byte offsets
+    const unsigned long long plane_bytes =
+        (unsigned long long)round_up((size_t)p->nx, TILE_X) * (unsigned long long)p->ny * elem_size(p->precision);
+    if (plane_bytes >= (1ull << 32)) return LBM_EINVAL;
     const double r[6] = {p->s_rho, p->s_e, p->s_zeta, p->s_j, p->s_q, p->s_nu};
     for (double v : r)
         if (!(v > 0.0 && v < 2.0)) return LBM_EINVAL;
@@ -188,6 +192,7 @@ void fill_desc(Instance *h)
     d.b4 = p.b / 4.0;
     d.RT = p.R * p.T;
     d.G = p.G;
+    d.two_over_G = 2.0 / p.G;
     d.s_e = p.s_e;
     d.s_z = p.s_zeta;
     d.s_q = p.s_q;

@@ -40,8 +40,8 @@ struct InstDev {
     int n_chunk;                   // steps this instance takes in the current chunk
     int tiles_x;                   // tiles per tile row for the current variant
     int n_bubbles;
-    // Eq. 15 and Eq. 13 constants
-    double a, b4, RT, G;
+    // Eq. 15 and Eq. 13 constants (two_over_G = 2 / (G c^2) with c = 1)
+    double a, b4, RT, G, two_over_G;
     // relaxation rates of Eq. 2 that act on non-conserved moments
     double s_e, s_z, s_q, s_nu;
     // Li's term after (I - Lambda/2): s_e * 0.75 eps and s_zeta * 0.75 eps

@@ -33,6 +33,73 @@ namespace {
 
 constexpr int NXCD = 8;
 
+// Population and psi buffers are reached through descriptors, so the compiler
+// sees generic pointers and would emit flat memory instructions, which also
+// count against the LDS wait counter and serialise the LDS reads behind the
+// outstanding population loads.  Casting to the global address space gives
+// global loads and stores.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> global_ptr(void *p)
+{
+    return (gptr<T>)p;
+}
+
+// A wavefront always works on one row, so the address of a population is a
+// wave-uniform row base (plane base + row offset, kept in scalar registers)
+// plus a per-lane byte offset below 4 GiB (every plane is under 4 GiB, checked
+// when an instance is created).  Written this way the loads and stores take
+// the scalar-base + 32-bit-offset form and all nine planes share one offset
+// register, instead of costing two address registers per access.
+template <typename T>
+__device__ __forceinline__ T ld(gptr<const char> row_base, unsigned lane_off)
+{
+    return *(gptr<const T>)(row_base + lane_off);
+}
+
+template <typename T>
+__device__ __forceinline__ void st(gptr<char> row_base, unsigned lane_off, T v)
+{
+    *(gptr<T>)(row_base + lane_off) = v;
+}
+
+// Index of the calling thread's wavefront, as a scalar.
+__device__ __forceinline__ int wave_index()
+{
+    return __builtin_amdgcn_readfirstlane(threadIdx.x / TILE_X);
+}
+
+// x / 9 and x / 6 as x * hi + x * lo, with hi + lo the reciprocal to twice the
+// working precision: one rounding of a nearly exact quotient, so the result is
+// the correctly rounded quotient except in rare near-ties and, unlike x * hi
+// alone, has no systematic bias.
+template <typename T>
+struct Third;
+template <>
+struct Third<float> {
+    static constexpr float r9_hi = 0x1.c71c72p-4f, r9_lo = -0x1.c71c72p-31f;
+    static constexpr float r6_hi = 0x1.555556p-3f, r6_lo = -0x1.555556p-28f;
+};
+template <>
+struct Third<double> {
+    static constexpr double r9_hi = 0x1.c71c71c71c71cp-4, r9_lo = 0x1.c71c71c71c71cp-58;
+    static constexpr double r6_hi = 0x1.5555555555555p-3, r6_lo = 0x1.5555555555555p-57;
+};
+
+template <typename T>
+__device__ __forceinline__ T div9(T x)
+{
+    return fma(x, Third<T>::r9_hi, x * Third<T>::r9_lo);
+}
+
+template <typename T>
+__device__ __forceinline__ T div6(T x)
+{
+    return fma(x, Third<T>::r6_hi, x * Third<T>::r6_lo);
+}
+
 // Block b of a grid of nblocks (a multiple of NXCD) runs tile xcd_tile(b):
 // consecutive dispatch slots of one XCD take consecutive tiles.
 __device__ __forceinline__ int xcd_tile(int b, int nblocks)
@@ -72,10 +139,10 @@ __device__ __forceinline__ T pseudopotential(T rho, const InstDev &d)
     if (EOS64) {
         const double r = (double)rho;
         const double p = eos_pressure<double>(r, d.RT, d.a, d.b4);
-        return (T)sqrt(2.0 * (p - r * (1.0 / 3.0)) / d.G);
+        return (T)sqrt((p - r * (1.0 / 3.0)) * d.two_over_G);
     } else {
         const T p = eos_pressure<T>(rho, (T)d.RT, (T)d.a, (T)d.b4);
-        return sqrt(T(2) * (p - rho * T(1.0 / 3.0)) / (T)d.G);
+        return sqrt((p - rho * T(1.0 / 3.0)) * (T)d.two_over_G);
     }
 }
 
@@ -105,12 +172,14 @@ __global__ __launch_bounds__(BLOCK) void psi_pass_kernel(const InstDev *__restri
     const Tile tl = tiles[t];
     const InstDev &d = insts[tl.inst];
     if (s >= d.n_chunk) return;
-    const T *__restrict__ f = (const T *)d.f[src_buffer(d, s)];
-    T *__restrict__ psi = (T *)d.psi;
-    const long long P = d.plane;
+    const gptr<const char> f = global_ptr<const char>(d.f[src_buffer(d, s)]);
+    const gptr<char> psi = global_ptr<char>(d.psi);
+    const unsigned long long PB = (unsigned long long)d.plane * sizeof(T);
+    const unsigned long long RB = (unsigned long long)d.pitch * sizeof(T);
     const int lx = threadIdx.x & (TILE_X - 1);
-    const int g = threadIdx.x / TILE_X;
+    const int g = wave_index();
     const int x = tl.x0 + lx;
+    const unsigned xo = (unsigned)x * sizeof(T);
     const bool track = s >= 0 && d.walls && (tl.y0 == 0 || tl.y0 + ROW_GROUPS * RY >= d.ny);
     bool bad = false;
     double wmax = -INFINITY;
@@ -121,10 +190,10 @@ __global__ __launch_bounds__(BLOCK) void psi_pass_kernel(const InstDev *__restri
         const int y = tl.y0 + g * RY + r;
         rho[r] = T(0);
         if (x < d.nx && y < d.ny) {
-            const long long i = (long long)y * d.pitch + x;
+            const gptr<const char> rb = f + (unsigned long long)y * RB;
             T v[9];
 #pragma unroll
-            for (int a = 0; a < 9; ++a) v[a] = f[a * P + i];
+            for (int a = 0; a < 9; ++a) v[a] = ld<T>(rb + a * PB, xo);
             rho[r] = density<T>(v);
         }
     }
@@ -132,9 +201,8 @@ __global__ __launch_bounds__(BLOCK) void psi_pass_kernel(const InstDev *__restri
     for (int r = 0; r < RY; ++r) {
         const int y = tl.y0 + g * RY + r;
         if (x < d.nx && y < d.ny) {
-            const long long i = (long long)y * d.pitch + x;
             const T ps = pseudopotential<T, EOS64>(rho[r], d);
-            psi[i] = ps;
+            st<T>(psi + (unsigned long long)y * RB, xo, ps);
             bad |= !finite_value(ps);
             if (track && (y == 0 || y == d.ny - 1))
                 wmax = fmax(wmax, eos_pressure<double>((double)rho[r], d.RT, d.a, d.b4));
@@ -233,14 +301,14 @@ __device__ __forceinline__ void collide_site(T f[9], T psi_c, T Fx, T Fy, const 
     // reciprocal rounded low (or high) would shrink (or grow) the total mass
     // and momentum by the same relative amount at every step, a drift of
     // 5.5e-17 (binary64) or 7.5e-9 (binary32) per step.  A correctly rounded
-    // quotient has no such bias.  The other moments relax, so a bias there
-    // does not accumulate.
-    const T a0 = rho / T(9);
+    // quotient (div9, div6) has no such bias.  The other moments relax, so a
+    // bias there does not accumulate.
+    const T a0 = div9(rho);
     const T a1 = n1 * T(1.0 / 36.0);
     const T a2 = n2 * T(1.0 / 36.0);
-    const T a3 = (jx + Fx) / T(6);
+    const T a3 = div6(jx + Fx);
     const T a4 = n4 * T(1.0 / 12.0);
-    const T a5 = (jy + Fy) / T(6);
+    const T a5 = div6(jy + Fy);
     const T a6 = n6 * T(1.0 / 12.0);
     const T a7 = n7 * T(0.25);
     const T a8 = n8 * T(0.25);
@@ -283,8 +351,9 @@ __device__ __forceinline__ void interaction_force(const T *rS, const T *rC, cons
 // neighbour wraps, or, through a wall, the population returns to (x, y) as
 // the opposite one (halfway bounce-back).
 template <typename T>
-__device__ __forceinline__ void push_store(T *__restrict__ fo, long long P, const T v[9], int x, int xe,
-                                           int xw, int y, int ny, int pitch, int walls)
+__device__ __forceinline__ void push_store(gptr<char> fo, unsigned long long PB, const T v[9], unsigned xo,
+                                           unsigned xeo, unsigned xwo, int y, int ny,
+                                           unsigned long long row_bytes, int walls)
 {
     const bool top = (y == ny - 1), bot = (y == 0);
     int yn = y + 1, ys = y - 1;
@@ -292,28 +361,29 @@ __device__ __forceinline__ void push_store(T *__restrict__ fo, long long P, cons
         if (top) yn = 0;
         if (bot) ys = ny - 1;
     }
-    const long long rc = (long long)y * pitch;
-    const long long rn = (long long)yn * pitch, rs = (long long)ys * pitch;
-    fo[0 * P + rc + x] = v[0];
-    fo[1 * P + rc + xe] = v[1];
-    fo[3 * P + rc + xw] = v[3];
+    const gptr<char> rc = fo + (unsigned long long)y * row_bytes;
+    const gptr<char> rn = fo + (unsigned long long)yn * row_bytes;
+    const gptr<char> rs = fo + (unsigned long long)ys * row_bytes;
+    st<T>(rc, xo, v[0]);
+    st<T>(rc + 1 * PB, xeo, v[1]);
+    st<T>(rc + 3 * PB, xwo, v[3]);
     if (walls && top) {
-        fo[4 * P + rc + x] = v[2];
-        fo[7 * P + rc + x] = v[5];
-        fo[8 * P + rc + x] = v[6];
+        st<T>(rc + 4 * PB, xo, v[2]);
+        st<T>(rc + 7 * PB, xo, v[5]);
+        st<T>(rc + 8 * PB, xo, v[6]);
     } else {
-        fo[2 * P + rn + x] = v[2];
-        fo[5 * P + rn + xe] = v[5];
-        fo[6 * P + rn + xw] = v[6];
+        st<T>(rn + 2 * PB, xo, v[2]);
+        st<T>(rn + 5 * PB, xeo, v[5]);
+        st<T>(rn + 6 * PB, xwo, v[6]);
     }
     if (walls && bot) {
-        fo[2 * P + rc + x] = v[4];
-        fo[5 * P + rc + x] = v[7];
-        fo[6 * P + rc + x] = v[8];
+        st<T>(rc + 2 * PB, xo, v[4]);
+        st<T>(rc + 5 * PB, xo, v[7]);
+        st<T>(rc + 6 * PB, xo, v[8]);
     } else {
-        fo[4 * P + rs + x] = v[4];
-        fo[7 * P + rs + xw] = v[7];
-        fo[8 * P + rs + xe] = v[8];
+        st<T>(rs + 4 * PB, xo, v[4]);
+        st<T>(rs + 7 * PB, xwo, v[7]);
+        st<T>(rs + 8 * PB, xeo, v[8]);
     }
 }
 
@@ -335,11 +405,12 @@ __global__ __launch_bounds__(BLOCK) void collide_stream_kernel(const InstDev *__
     const InstDev &d = insts[tl.inst];
     if (s >= d.n_chunk) return;
     const int sb = src_buffer(d, s);
-    const T *__restrict__ f = (const T *)d.f[sb];
-    T *__restrict__ fo = (T *)d.f[sb ^ 1];
-    const T *__restrict__ psi = (const T *)d.psi;
-    const long long P = d.plane;
-    const int nx = d.nx, ny = d.ny, pitch = d.pitch;
+    const gptr<const char> f = global_ptr<const char>(d.f[sb]);
+    const gptr<char> fo = global_ptr<char>(d.f[sb ^ 1]);
+    const gptr<const char> psi = global_ptr<const char>(d.psi);
+    const unsigned long long PB = (unsigned long long)d.plane * sizeof(T);
+    const unsigned long long RB = (unsigned long long)d.pitch * sizeof(T);
+    const int nx = d.nx, ny = d.ny;
 
     // psi of the tile and a one-site ring; x wraps, y wraps or mirrors at walls
     for (int k = threadIdx.x; k < (TY + 2) * LW; k += BLOCK) {
@@ -354,33 +425,34 @@ __global__ __launch_bounds__(BLOCK) void collide_stream_kernel(const InstDev *__
             gy %= ny;
             if (gy < 0) gy += ny;
         }
-        sp[k] = psi[(long long)gy * pitch + gx];
+        sp[k] = ld<T>(psi + (unsigned long long)gy * RB, (unsigned)gx * sizeof(T));
     }
     __syncthreads();
 
     const Rates<T> R = load_rates<T>(d);
     const int lx = threadIdx.x & (TILE_X - 1);
-    const int g = threadIdx.x / TILE_X;
+    const int g = wave_index();
     const int x = tl.x0 + lx;
     if (x >= nx) return;
-    const int xe = (x + 1 == nx) ? 0 : x + 1;
-    const int xw = (x == 0) ? nx - 1 : x - 1;
+    const unsigned xo = (unsigned)x * sizeof(T);
+    const unsigned xeo = (unsigned)((x + 1 == nx) ? 0 : x + 1) * sizeof(T);
+    const unsigned xwo = (unsigned)((x == 0) ? nx - 1 : x - 1) * sizeof(T);
 
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         const int ly = g * RY + r;
         const int y = tl.y0 + ly;
         if (y >= ny) break;
-        const long long rc = (long long)y * pitch;
+        const gptr<const char> rb = f + (unsigned long long)y * RB;
         T v[9];
 #pragma unroll
-        for (int a = 0; a < 9; ++a) v[a] = f[a * P + rc + x];
+        for (int a = 0; a < 9; ++a) v[a] = ld<T>(rb + a * PB, xo);
 
         T pc, Fx, Fy;
         interaction_force<T>(sp + ly * LW, sp + (ly + 1) * LW, sp + (ly + 2) * LW, lx + 1, -(T)d.G, pc,
                              Fx, Fy);
         collide_site<T>(v, pc, Fx, Fy, R);
-        push_store<T>(fo, P, v, x, xe, xw, y, ny, pitch, d.walls);
+        push_store<T>(fo, PB, v, xo, xeo, xwo, y, ny, RB, d.walls);
     }
 }
 
@@ -420,19 +492,22 @@ __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict_
     const InstDev &d = insts[tl.inst];
     if (s >= d.n_chunk) return;
     const int sb = src_buffer(d, s);
-    const T *__restrict__ f = (const T *)d.f[sb];
-    T *__restrict__ fo = (T *)d.f[sb ^ 1];
-    const long long P = d.plane;
-    const int nx = d.nx, ny = d.ny, pitch = d.pitch, walls = d.walls;
+    const gptr<const char> f = global_ptr<const char>(d.f[sb]);
+    const gptr<char> fo = global_ptr<char>(d.f[sb ^ 1]);
+    const unsigned long long PB = (unsigned long long)d.plane * sizeof(T);
+    const unsigned long long RB = (unsigned long long)d.pitch * sizeof(T);
+    const int nx = d.nx, ny = d.ny, walls = d.walls;
     const int lane = threadIdx.x & (TILE_X - 1);
-    const int w = threadIdx.x / TILE_X;
+    const int w = wave_index();
     const int x = tl.x0 + lane;
     const int xl = x < nx ? x : x % nx;                       // column this lane loads
     const bool halo = lane < 2;                               // lanes that also load a ring column
     const int xh = lane == 0 ? (tl.x0 == 0 ? nx - 1 : tl.x0 - 1) : (tl.x0 + TILE_X) % nx;
     const int hslot = lane == 0 ? 0 : LW - 1;
-    const int xe = (x + 1 >= nx) ? 0 : x + 1;
-    const int xw = (x == 0) ? nx - 1 : x - 1;
+    const unsigned xo = (unsigned)x * sizeof(T), xlo = (unsigned)xl * sizeof(T);
+    const unsigned xho = (unsigned)xh * sizeof(T);
+    const unsigned xeo = (unsigned)((x + 1 >= nx) ? 0 : x + 1) * sizeof(T);
+    const unsigned xwo = (unsigned)((x == 0) ? nx - 1 : x - 1) * sizeof(T);
     const int y_end = min(tl.y0 + H, ny);                     // rows collided: [y0, y_end)
     const bool track = walls && (tl.y0 == 0 || tl.y0 + H >= ny);
     const Rates<T> R = load_rates<T>(d);
@@ -450,18 +525,30 @@ __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict_
         int mr = l;                                           // memory row (ghost rows mirror or wrap)
         if (walls) mr = mr < 0 ? 0 : (mr > ny - 1 ? ny - 1 : mr);
         else mr = mr < 0 ? mr + ny : (mr >= ny ? mr - ny : mr);
-        T fn[9], fh[9];
+        // Loads of the new row are issued first and stay in flight while the
+        // row loaded two iterations ago is collided.  The ring-column loads
+        // (lanes 0 and 1) go out before them and are reduced to psi first, so
+        // their registers are free during the collision.
+        const gptr<const char> rb = f + (unsigned long long)mr * RB;
+        T fn[9];
 #pragma unroll
-        for (int a = 0; a < 9; ++a) fn[a] = fh[a] = T(0);
+        for (int a = 0; a < 9; ++a) fn[a] = T(0);
+        T rho_h = T(0);
+        if (do_load && halo) {
+            T fh[9];
+#pragma unroll
+            for (int a = 0; a < 9; ++a) fh[a] = ld<T>(rb + a * PB, xho);
+            rho_h = density<T>(fh);
+        }
         if (do_load) {
-            const long long i = (long long)mr * pitch + xl;
 #pragma unroll
-            for (int a = 0; a < 9; ++a) fn[a] = f[a * P + i];
-            if (halo) {
-                const long long ih = (long long)mr * pitch + xh;
-#pragma unroll
-                for (int a = 0; a < 9; ++a) fh[a] = f[a * P + ih];
-            }
+            for (int a = 0; a < 9; ++a) fn[a] = ld<T>(rb + a * PB, xlo);
+        }
+        T *row = ring + ((l + 2 * RING) % RING) * LW;
+        if (do_load && halo) {
+            const T ph = pseudopotential<T, EOS64>(rho_h, d);
+            row[hslot] = ph;
+            bad |= !finite_value(ph);
         }
 
         // collide the row loaded two iterations ago
@@ -473,21 +560,15 @@ __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict_
             T pc, Fx, Fy;
             interaction_force<T>(rS, rC, rN, lane + 1, mG, pc, Fx, Fy);
             collide_site<T>(fb, pc, Fx, Fy, R);
-            push_store<T>(fo, P, fb, x, xe, xw, c, ny, pitch, walls);
+            push_store<T>(fo, PB, fb, xo, xeo, xwo, c, ny, RB, walls);
         }
 
         // psi of the row loaded now
         if (do_load) {
-            T *row = ring + ((l + 2 * RING) % RING) * LW;
             const T rho = density<T>(fn);
             const T ps = pseudopotential<T, EOS64>(rho, d);
             row[lane + 1] = ps;
             bad |= !finite_value(ps);
-            if (halo) {
-                const T ph = pseudopotential<T, EOS64>(density<T>(fh), d);
-                row[hslot] = ph;
-                bad |= !finite_value(ph);
-            }
             if (track && (l == 0 || l == ny - 1) && l >= tl.y0 && l < y_end && x < nx)
                 wmax = fmax(wmax, eos_pressure<double>((double)rho, d.RT, d.a, d.b4));
         }

@@ -13,7 +13,8 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "liblbm.so")
+# LBM_LIB selects another build of the same library (e.g. a tuning experiment)
+LIB_PATH = os.environ.get("LBM_LIB") or os.path.join(_HERE, "_lib", "liblbm.so")
 
 FP64, FP32, FP32_MIXED = 0, 1, 2
 _PREC = {"fp64": FP64, "fp32": FP32, "fp32_mixed": FP32_MIXED, FP64: FP64, FP32: FP32,
