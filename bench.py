@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--no-fp64-plain", action="store_true")
     ap.add_argument("--variant", type=int, default=-1, help="tile variant; -1 autotunes")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-served", action="store_true", help="skip the served-batch latency run")
+    ap.add_argument("--served-requests", type=int, default=512)
+    ap.add_argument("--served-budget-gb", type=float, default=8.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run liblbm's plain copy kernel over MIB MiB, 5 times, and exit "
                          "(reference for the memory-traffic counters)")
@@ -137,6 +140,37 @@ def fp64_plain(L, device, steps):
     for s in sims:
         s.close()
     return len(sims) * 256 * 256 * steps / dt / 1e6
+
+
+def served_run(device, n_requests, budget_gb, load=0.8, chunk=500, seed=0):
+    """The served batch: n_requests requests of the served-batch trace (sides
+    log-uniform in [64, 1024], aspect 1, 4/3 or 2, half periodic bubbles and
+    half wall-bounded collapses, T/Tc in [0.6, 0.9], 5,000-40,000 steps),
+    Poisson arrivals at a rate that loads the GPU to `load` of the throughput
+    measured by the autotuner on the first 16 requests."""
+    import numpy as np
+    from paper_1605_01800_amd import inputs, serving
+    trace = inputs.request_trace(n_requests, seed)
+    reqs0 = serving.make_requests(trace, [0.0] * n_requests)
+    be = serving.GpuBackend(precision="fp32", device=device, max_instances=64, max_tiles=1 << 19)
+    variant, cal_mlups = be.autotune(reqs0[:16])
+    work = np.mean([r.sites * r.steps for r in reqs0])
+    rate = load * cal_mlups * 1e6 / work
+    arrivals = inputs.poisson_arrivals(n_requests, rate, seed + 1)
+    reqs = serving.make_requests(trace, arrivals)
+    srv = serving.Server(be, budget_bytes=int(budget_gb * 1e9), max_slots=64, chunk_steps=chunk)
+    results, stats = srv.run(reqs)
+    be.close()
+    bad = [r.id for r in results if r.diag.get("nonfinite")]
+    from paper_1605_01800_amd import lbm as L
+    return {"requests": len(results), "arrival_rate_per_s": round(rate, 3), "load": load,
+            "calibrated_mlups": round(cal_mlups, 1), "tile": L.variant_names()[variant],
+            "budget_GB": budget_gb, "chunk_steps": chunk, "wall_s": round(stats["wall_s"], 3),
+            "busy_s": round(stats["busy_s"], 3), "aggregate_mlups": round(stats["mlups"], 1),
+            "busy_mlups": round(stats["busy_mlups"], 1), "p50_s": round(stats["p50_s"], 4),
+            "p99_s": round(stats["p99_s"], 4), "mean_s": round(stats["mean_s"], 4),
+            "peak_resident_GB": round(stats["peak_resident_bytes"] / 1e9, 3),
+            "peak_slots": stats["peak_slots"], "nonfinite_requests": bad}
 
 
 def main():
@@ -260,6 +294,14 @@ def main():
         out["fp64_plain_mlups"] = round(plain, 1)
         out["speedup_vs_fp64_plain"] = round(mlups / plain, 2)
         print("# fp64 plain per-instance %.0f MLUPS" % plain, file=sys.stderr, flush=True)
+
+    if args.workload == "laplace_sweep" and not args.no_served:
+        sv = served_run(device, args.served_requests, args.served_budget_gb)
+        out["served"] = sv
+        out["p50_s"] = sv["p50_s"]
+        out["p99_s"] = sv["p99_s"]
+        print("# served %d requests: %.0f MLUPS aggregate, p50 %.3f s, p99 %.3f s"
+              % (sv["requests"], sv["aggregate_mlups"], sv["p50_s"], sv["p99_s"]), file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

@@ -323,6 +323,12 @@ int read_latch(Instance *h)
 int batch_sync(Batch *b)
 {
     if (b->dirty) {
+        // a new composition makes the cached graphs unreachable (their key
+        // holds the tile and instance counts); release them once idle
+        if (!b->graphs.empty()) {
+            TRYHIP(hipStreamSynchronize(b->stream));
+            drop_graphs(b->graphs);
+        }
         std::vector<Tile> tl;
         b->descs.clear();
         for (size_t i = 0; i < b->members.size(); ++i) {

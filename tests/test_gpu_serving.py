@@ -1,0 +1,46 @@
+"""The served path on the GPU: every request's final state is bitwise the
+same as the same request stepped alone, whatever else was resident."""
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+L = pytest.importorskip("paper_1605_01800_amd.lbm")
+from paper_1605_01800_amd.serving import GpuBackend, Request, Server  # noqa: E402
+
+
+def _requests():
+    return [
+        Request(id=0, nx=64, ny=64, walls=False, T_over_Tc=0.7, steps=700, bubbles=[(31.5, 31.5, 12.0)], arrival=0.0),
+        Request(id=1, nx=200, ny=90, walls=True, T_over_Tc=0.6, steps=450, bubbles=[(99.5, 30.0, 18.0)],
+                delta=0.02, arrival=0.0),
+        Request(id=2, nx=77, ny=129, walls=False, T_over_Tc=0.85, steps=1000, bubbles=[(38.0, 64.0, 15.0)],
+                arrival=0.02),
+        Request(id=3, nx=130, ny=66, walls=True, T_over_Tc=0.75, steps=333, bubbles=[(64.5, 22.0, 12.0)],
+                delta=0.01, arrival=0.05),
+        Request(id=4, nx=96, ny=96, walls=False, T_over_Tc=0.9, steps=260, bubbles=[(47.5, 47.5, 20.0)],
+                arrival=0.05),
+    ]
+
+
+@pytest.mark.parametrize("budget_mb", [1000, 12])
+def test_served_results_equal_alone_bitwise(budget_mb):
+    variant = L.variant_names().index("fused-64x16")
+    be = GpuBackend(precision="fp32", max_instances=8, max_tiles=1 << 14, variant=variant, keep_state=True)
+    srv = Server(be, budget_bytes=budget_mb * 10 ** 6, max_slots=8, chunk_steps=128)
+    results, stats = srv.run(_requests())
+    be.close()
+    assert len(results) == 5
+    assert stats["peak_resident_bytes"] <= budget_mb * 10 ** 6
+    for r, q in zip(results, _requests()):
+        p = L.make_params(q.nx, q.ny, T_over_Tc=q.T_over_Tc, walls=q.walls, precision="fp32", tau_nu=q.tau_nu)
+        s = L.Sim(p)
+        s.set_variant(variant)
+        s.init_bubble(q.bubbles, W=q.W, delta=q.delta)
+        s.step(q.steps)
+        ref = s.populations().cpu()
+        d = s.diag()
+        s.close()
+        assert r.diag["step"] == q.steps
+        assert torch.equal(r.state, ref), q.id
+        assert r.diag["radius"] == d["radius"]
