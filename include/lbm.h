@@ -124,6 +124,14 @@ int lbm_init_bubble(void *handle, const lbm_bubble *b, int nb, int slab_rows,
                     double rho_l, double rho_g, double W, double delta,
                     double noise_amp, uint64_t seed);
 
+/* Initial state at rest from a density field: f_a = w_a rho (w = 4/9, 1/9,
+ * 1/36), for any initial density, e.g. the uniform liquid with a perturbed
+ * line of the cavitation-inception run (Section 3.2).  d_rho: nx*ny binary64
+ * values on the device, row-major [y][x].  rho_l and rho_g are kept for the
+ * gas-fraction diagnostics (no bubbles are assumed: n_bubbles = 0).  Resets
+ * the step counter, the wall-pressure peak and the non-finite latch. */
+int lbm_init_density(void *handle, const void *d_rho, double rho_l, double rho_g);
+
 /* Enqueues n >= 0 timesteps (Eqs. 15, 13, 7, 6, 4, 14, 3, 5).  Asynchronous. */
 int lbm_step(void *handle, int64_t n);
 
@@ -137,7 +145,11 @@ int lbm_macros(void *handle, void *d_rho, void *d_ux, void *d_uy, void *d_p,
 
 /* Copies the current post-streaming populations to / from a device buffer of
  * 9*nx*ny values in the population precision, layout f[a][y][x].  Asynchronous.
- * lbm_set_populations resets the step counter and the latch like an init. */
+ * The state is stored internally as deviations g_a = f_a - w_a rho_ref from the
+ * rest equilibrium of a reference density (rho_l of the last lbm_init_bubble
+ * or lbm_init_density, 0 for a handle never initialised); these calls convert,
+ * so the buffer holds plain populations f_a.  lbm_set_populations keeps the
+ * current reference and resets the step counter and the latch like an init. */
 int lbm_get_populations(void *handle, void *d_out);
 int lbm_set_populations(void *handle, const void *d_in);
 

@@ -27,6 +27,10 @@ inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 size_t elem_size(int prec) { return prec == LBM_FP64 ? 8 : 4; }
 
+// The population shift reference, rounded to the storage precision so that
+// stored deviations and the reconstruction rho = rho_ref + sum g agree.
+double storage_value(int prec, double v) { return prec == LBM_FP64 ? v : (double)(float)v; }
+
 struct Layout {
     size_t desc, tiles, f0, f1, psi, partials, flag, wall_keys, wall_run, result, total;
     int pitch;
@@ -516,6 +520,7 @@ int lbm_init_bubble(void *handle, const lbm_bubble *b, int nb, int slab_rows, do
     d.n_bubbles = nbub;
     d.rho_l = rho_l;
     d.rho_g = rho_g;
+    d.rho_ref = storage_value(h->p.precision, rho_l);
     for (int k = 0; k < LBM_MAX_BUBBLES; ++k) {
         d.bx[k] = k < nbub ? b[k].x0 : 0.0;
         d.by[k] = k < nbub ? b[k].y0 : 0.0;
@@ -527,6 +532,31 @@ int lbm_init_bubble(void *handle, const lbm_bubble *b, int nb, int slab_rows, do
     TRYHIP(launch_reset_diag(h->d_desc, st));
     TRYHIP(launch_init(h->p.precision, h->d_desc, slab_rows, b, nbub, rho_l, rho_g, W, delta,
                        noise_amp, seed, (long long)h->p.nx * h->p.ny, st));
+    h->has_state = true;
+    h->sticky = LBM_OK;
+    return LBM_OK;
+}
+
+int lbm_init_density(void *handle, const void *d_rho, double rho_l, double rho_g)
+{
+    Instance *h = (Instance *)handle;
+    if (!h || !d_rho || !(rho_l > 0) || !(rho_g > 0)) return LBM_EINVAL;
+    h->n_bubbles = 0;
+    InstDev &d = h->desc;
+    d.cur = 0;
+    d.step = 0;
+    d.n_chunk = 0;
+    d.n_bubbles = 0;
+    d.rho_l = rho_l;
+    d.rho_g = rho_g;
+    d.rho_ref = storage_value(h->p.precision, rho_l);
+    h->desc_dirty = true;
+    if (h->batch) h->batch->dirty = true;
+    TRY(sync_own(h));
+    hipStream_t st = stream_of(h);
+    TRYHIP(launch_reset_diag(h->d_desc, st));
+    TRYHIP(launch_init_density(h->p.precision, h->d_desc, (const double *)d_rho,
+                               (long long)h->p.nx * h->p.ny, st));
     h->has_state = true;
     h->sticky = LBM_OK;
     return LBM_OK;
@@ -677,7 +707,7 @@ struct CkptHeader {
     int64_t step;
     int32_t n_bubbles, pad;
     lbm_bubble bubbles[LBM_MAX_BUBBLES];
-    double rho_l, rho_g;
+    double rho_l, rho_g, rho_ref;
     unsigned long long wall_run[2];
 };
 
@@ -709,6 +739,7 @@ int lbm_save(void *handle, void *host_buf, size_t bytes)
     for (int k = 0; k < h->n_bubbles; ++k) hd.bubbles[k] = h->bubbles[k];
     hd.rho_l = h->desc.rho_l;
     hd.rho_g = h->desc.rho_g;
+    hd.rho_ref = h->desc.rho_ref;
     TRYHIP(hipMemcpy(hd.wall_run, h->desc.wall_run, sizeof hd.wall_run, hipMemcpyDeviceToHost));
     memcpy(host_buf, &hd, sizeof hd);
     const size_t es = elem_size(h->p.precision);
@@ -741,6 +772,7 @@ int lbm_load(void *handle, const void *host_buf, size_t bytes)
     d.n_bubbles = hd.n_bubbles;
     d.rho_l = hd.rho_l;
     d.rho_g = hd.rho_g;
+    d.rho_ref = hd.rho_ref;
     for (int k = 0; k < LBM_MAX_BUBBLES; ++k) {
         h->bubbles[k] = hd.bubbles[k];
         d.bx[k] = k < hd.n_bubbles ? hd.bubbles[k].x0 : 0.0;

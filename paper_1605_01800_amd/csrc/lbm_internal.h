@@ -47,6 +47,9 @@ struct InstDev {
     // Li's term after (I - Lambda/2): s_e * 0.75 eps and s_zeta * 0.75 eps
     double li_e, li_z;
     double rho_l, rho_g;           // gas-fraction densities
+    // Populations are stored shifted by the rest equilibrium of rho_ref:
+    // g_a = f_a - w_a rho_ref (rho_ref representable in the storage precision)
+    double rho_ref;
     double bx[LBM_MAX_BUBBLES], by[LBM_MAX_BUBBLES];
 };
 
@@ -86,6 +89,8 @@ hipError_t launch_chunk_end(const InstDev *d_inst, int ninst, hipStream_t st);
 hipError_t launch_init(int prec, const InstDev *d_inst, int slab_rows, const lbm_bubble *b, int nb,
                        double rho_l, double rho_g, double W, double delta, double noise_amp,
                        uint64_t seed, long long nsites, hipStream_t st);
+hipError_t launch_init_density(int prec, const InstDev *d_inst, const double *rho, long long nsites,
+                              hipStream_t st);
 hipError_t launch_macros(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles,
                          int ntiles, void *rho, void *ux, void *uy, double *p, hipStream_t st);
 hipError_t launch_reduce(const InstDev *d_inst, int ntiles, hipStream_t st);

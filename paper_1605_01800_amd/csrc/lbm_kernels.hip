@@ -114,7 +114,14 @@ __device__ __forceinline__ int src_buffer(const InstDev &d, int s)
     return s < 0 ? d.cur : ((d.cur + s) & 1);
 }
 
-// rho = sum_a f_a, always in this order.
+// Populations are stored as g_a = f_a - w_a rho_ref, the deviation from the
+// rest equilibrium of a reference density (the liquid density of the run).
+// In uniform regions every site computes nearly the same numbers, so rounding
+// errors add up coherently instead of averaging out; with the shift they act on
+// deviations instead of on the populations themselves, which makes them about
+// |f - w rho_ref| / |f| smaller (three orders of magnitude in the liquid).
+//
+// sum_a g_a = rho - rho_ref, always in this order.
 template <typename T>
 __device__ __forceinline__ T density(const T v[9])
 {
@@ -131,16 +138,18 @@ __device__ __forceinline__ T eos_pressure(T rho, T RT, T a, T b4)
     return rho * RT * num / (om * om * om) - a * rho * rho;
 }
 
-// Pseudopotential, Eq. 13 with c = 1 and c_s^2 = 1/3.  EOS64 evaluates the
+// Pseudopotential, Eq. 13 with c = 1 and c_s^2 = 1/3, of a site whose shifted
+// populations sum to dm (rho = rho_ref + dm).  EOS64 forms rho and evaluates the
 // pressure and the root in binary64 whatever T is.
 template <typename T, bool EOS64>
-__device__ __forceinline__ T pseudopotential(T rho, const InstDev &d)
+__device__ __forceinline__ T pseudopotential(T dm, const InstDev &d)
 {
     if (EOS64) {
-        const double r = (double)rho;
+        const double r = d.rho_ref + (double)dm;
         const double p = eos_pressure<double>(r, d.RT, d.a, d.b4);
         return (T)sqrt((p - r * (1.0 / 3.0)) * d.two_over_G);
     } else {
+        const T rho = (T)d.rho_ref + dm;
         const T p = eos_pressure<T>(rho, (T)d.RT, (T)d.a, (T)d.b4);
         return sqrt((p - rho * T(1.0 / 3.0)) * (T)d.two_over_G);
     }
@@ -184,28 +193,28 @@ __global__ __launch_bounds__(BLOCK) void psi_pass_kernel(const InstDev *__restri
     bool bad = false;
     double wmax = -INFINITY;
 
-    T rho[RY];
+    T dm[RY];                                   // rho - rho_ref per row
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         const int y = tl.y0 + g * RY + r;
-        rho[r] = T(0);
+        dm[r] = T(0);
         if (x < d.nx && y < d.ny) {
             const gptr<const char> rb = f + (unsigned long long)y * RB;
             T v[9];
 #pragma unroll
             for (int a = 0; a < 9; ++a) v[a] = ld<T>(rb + a * PB, xo);
-            rho[r] = density<T>(v);
+            dm[r] = density<T>(v);
         }
     }
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         const int y = tl.y0 + g * RY + r;
         if (x < d.nx && y < d.ny) {
-            const T ps = pseudopotential<T, EOS64>(rho[r], d);
+            const T ps = pseudopotential<T, EOS64>(dm[r], d);
             st<T>(psi + (unsigned long long)y * RB, xo, ps);
             bad |= !finite_value(ps);
             if (track && (y == 0 || y == d.ny - 1))
-                wmax = fmax(wmax, eos_pressure<double>((double)rho[r], d.RT, d.a, d.b4));
+                wmax = fmax(wmax, eos_pressure<double>(d.rho_ref + (double)dm[r], d.RT, d.a, d.b4));
         }
     }
     if (bad) d.flag[0] = 1;
@@ -243,12 +252,17 @@ __device__ __forceinline__ Rates<T> load_rates(const InstDev &d)
     return r;
 }
 
-// f: post-streaming populations of the site (in), post-collision (out).
-// psi_c: psi at the site; Fx, Fy: force of Eq. 7.
+// f: shifted post-streaming populations g_a = f_a - w_a rho_ref of the site
+// (in), shifted post-collision populations (out).  psi_c: psi at the site;
+// Fx, Fy: force of Eq. 7.  The moments of g differ from those of f only in the
+// mass, e and zeta rows, by rho_ref (1, -2, 1) (the rest equilibrium's
+// moments), so every relaxation below is the one of Eq. 3 with those three
+// rows and their equilibria shifted alike.
 template <typename T>
-__device__ __forceinline__ void collide_site(T f[9], T psi_c, T Fx, T Fy, const Rates<T> &R)
+__device__ __forceinline__ void collide_site(T f[9], T psi_c, T Fx, T Fy, T rho_ref, const Rates<T> &R)
 {
-    const T rho = (((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7]))) + f[8];
+    const T dm = density<T>(f);                 // rho - rho_ref
+    const T rho = rho_ref + dm;
     const T jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
     const T jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
     const T inv_rho = T(1) / rho;
@@ -267,9 +281,10 @@ __device__ __forceinline__ void collide_site(T f[9], T psi_c, T Fx, T Fy, const 
     const T m7 = (f[1] - f[2]) + (f[3] - f[4]);
     const T m8 = (f[5] - f[6]) + (f[7] - f[8]);
 
-    // equilibria, Eq. 4
-    const T e1 = rho * (T(-2) + T(3) * v2);
-    const T e2 = rho * (T(1) - T(3) * v2);
+    // equilibria, Eq. 4 (e and zeta rows shifted by 2 rho_ref and -rho_ref,
+    // like m1 and m2: rho (-2 + 3 v^2) + 2 rho_ref, rho (1 - 3 v^2) - rho_ref)
+    const T e1 = T(3) * rho * v2 - T(2) * dm;
+    const T e2 = dm - T(3) * rho * v2;
     const T e4 = -rho * vx;
     const T e6 = -rho * vy;
     const T e7 = rho * (vx * vx - vy * vy);
@@ -287,7 +302,8 @@ __device__ __forceinline__ void collide_site(T f[9], T psi_c, T Fx, T Fy, const 
     const T q8 = R.h_nu * (vx * Fy + vy * Fx);
 
     // relaxation, Eq. 3.  rho and j are collision invariants up to the
-    // source: m0* = rho, m3* = jx + Fx, m5* = jy + Fy for any s_rho, s_j.
+    // source: m0* = rho (dm in shifted form), m3* = jx + Fx, m5* = jy + Fy for
+    // any s_rho, s_j.
     const T n1 = m1 - R.s_e * (m1 - e1) + q1;
     const T n2 = m2 - R.s_z * (m2 - e2) + q2;
     const T n4 = m4 - R.s_q * (m4 - e4) + q4;
@@ -303,7 +319,7 @@ __device__ __forceinline__ void collide_site(T f[9], T psi_c, T Fx, T Fy, const 
     // 5.5e-17 (binary64) or 7.5e-9 (binary32) per step.  A correctly rounded
     // quotient (div9, div6) has no such bias.  The other moments relax, so a
     // bias there does not accumulate.
-    const T a0 = div9(rho);
+    const T a0 = div9(dm);
     const T a1 = n1 * T(1.0 / 36.0);
     const T a2 = n2 * T(1.0 / 36.0);
     const T a3 = div6(jx + Fx);
@@ -451,7 +467,7 @@ __global__ __launch_bounds__(BLOCK) void collide_stream_kernel(const InstDev *__
         T pc, Fx, Fy;
         interaction_force<T>(sp + ly * LW, sp + (ly + 1) * LW, sp + (ly + 2) * LW, lx + 1, -(T)d.G, pc,
                              Fx, Fy);
-        collide_site<T>(v, pc, Fx, Fy, R);
+        collide_site<T>(v, pc, Fx, Fy, (T)d.rho_ref, R);
         push_store<T>(fo, PB, v, xo, xeo, xwo, y, ny, RB, d.walls);
     }
 }
@@ -533,12 +549,12 @@ __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict_
         T fn[9];
 #pragma unroll
         for (int a = 0; a < 9; ++a) fn[a] = T(0);
-        T rho_h = T(0);
+        T dm_h = T(0);
         if (do_load && halo) {
             T fh[9];
 #pragma unroll
             for (int a = 0; a < 9; ++a) fh[a] = ld<T>(rb + a * PB, xho);
-            rho_h = density<T>(fh);
+            dm_h = density<T>(fh);
         }
         if (do_load) {
 #pragma unroll
@@ -546,7 +562,7 @@ __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict_
         }
         T *row = ring + ((l + 2 * RING) % RING) * LW;
         if (do_load && halo) {
-            const T ph = pseudopotential<T, EOS64>(rho_h, d);
+            const T ph = pseudopotential<T, EOS64>(dm_h, d);
             row[hslot] = ph;
             bad |= !finite_value(ph);
         }
@@ -559,18 +575,18 @@ __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict_
             const T *rN = ring + ((c + 1 + 2 * RING) % RING) * LW;
             T pc, Fx, Fy;
             interaction_force<T>(rS, rC, rN, lane + 1, mG, pc, Fx, Fy);
-            collide_site<T>(fb, pc, Fx, Fy, R);
+            collide_site<T>(fb, pc, Fx, Fy, (T)d.rho_ref, R);
             push_store<T>(fo, PB, fb, xo, xeo, xwo, c, ny, RB, walls);
         }
 
         // psi of the row loaded now
         if (do_load) {
-            const T rho = density<T>(fn);
-            const T ps = pseudopotential<T, EOS64>(rho, d);
+            const T dm = density<T>(fn);
+            const T ps = pseudopotential<T, EOS64>(dm, d);
             row[lane + 1] = ps;
             bad |= !finite_value(ps);
             if (track && (l == 0 || l == ny - 1) && l >= tl.y0 && l < y_end && x < nx)
-                wmax = fmax(wmax, eos_pressure<double>((double)rho, d.RT, d.a, d.b4));
+                wmax = fmax(wmax, eos_pressure<double>(d.rho_ref + (double)dm, d.RT, d.a, d.b4));
         }
         __syncthreads();
 #pragma unroll
@@ -680,11 +696,32 @@ __global__ void init_kernel(const InstDev *inst, InitArgs A)
     T *f = (T *)d.f[d.cur];
     const long long j = (long long)y * d.pitch + x;
     const double w0 = 4.0 / 9.0, w1 = 1.0 / 9.0, w5 = 1.0 / 36.0;
-    f[j] = (T)(w0 * rho);
+    const double dev = rho - d.rho_ref;        // stored shifted by w_a rho_ref
+    f[j] = (T)(w0 * dev);
 #pragma unroll
-    for (int a = 1; a <= 4; ++a) f[a * d.plane + j] = (T)(w1 * rho);
+    for (int a = 1; a <= 4; ++a) f[a * d.plane + j] = (T)(w1 * dev);
 #pragma unroll
-    for (int a = 5; a <= 8; ++a) f[a * d.plane + j] = (T)(w5 * rho);
+    for (int a = 5; a <= 8; ++a) f[a * d.plane + j] = (T)(w5 * dev);
+}
+
+// f_a = w_a rho from a dense binary64 density field
+template <typename T>
+__global__ void init_density_kernel(const InstDev *inst, const double *__restrict__ rho_in)
+{
+    const InstDev &d = *inst;
+    const long long n = (long long)d.nx * d.ny;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int y = (int)(i / d.nx);
+    const int x = (int)(i - (long long)y * d.nx);
+    const double dev = rho_in[i] - d.rho_ref;
+    T *f = (T *)d.f[d.cur];
+    const long long j = (long long)y * d.pitch + x;
+    f[j] = (T)(4.0 / 9.0 * dev);
+#pragma unroll
+    for (int a = 1; a <= 4; ++a) f[a * d.plane + j] = (T)(1.0 / 9.0 * dev);
+#pragma unroll
+    for (int a = 5; a <= 8; ++a) f[a * d.plane + j] = (T)(1.0 / 36.0 * dev);
 }
 
 // ---------------------------------------------------------------------------
@@ -719,7 +756,8 @@ __global__ __launch_bounds__(BLOCK) void macros_kernel(const InstDev *__restrict
         T v[9];
 #pragma unroll
         for (int a = 0; a < 9; ++a) v[a] = f[a * P + i];
-        const T rho = (((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]))) + v[8];
+        const T dm = density<T>(v);
+        const T rho = (T)d.rho_ref + dm;
         const T jx = (v[1] - v[3]) + (v[5] - v[6]) + (v[8] - v[7]);
         const T jy = (v[2] - v[4]) + (v[5] + v[6]) - (v[7] + v[8]);
         auto ps = [&](int dx, int dy) -> T {
@@ -742,12 +780,12 @@ __global__ __launch_bounds__(BLOCK) void macros_kernel(const InstDev *__restrict
         if (rho_out) rho_out[o] = rho;
         if (ux_out) ux_out[o] = mx / rho;
         if (uy_out) uy_out[o] = my / rho;
-        if (p_out) p_out[o] = eos_pressure<double>((double)rho, d.RT, d.a, d.b4);
-        acc[0] += (double)rho;
+        if (p_out) p_out[o] = eos_pressure<double>(d.rho_ref + (double)dm, d.RT, d.a, d.b4);
+        acc[0] += d.rho_ref + (double)dm;
         acc[1] += (double)mx;
         acc[2] += (double)my;
         if (d.n_bubbles > 0) {
-            double frac = (d.rho_l - (double)rho) / (d.rho_l - d.rho_g);
+            double frac = (d.rho_l - (d.rho_ref + (double)dm)) / (d.rho_l - d.rho_g);
             frac = frac < 0.0 ? 0.0 : (frac > 1.0 ? 1.0 : frac);
             int best = 0;
             double bd = INFINITY;
@@ -806,8 +844,10 @@ __global__ void pack_kernel(const InstDev *inst, T *dense, int to_dense)
     const int x = (int)(i - (long long)y * d.nx);
     T *f = (T *)d.f[d.cur];
     const long long j = a * d.plane + (long long)y * d.pitch + x;
-    if (to_dense) dense[a * n + i] = f[j];
-    else f[j] = dense[a * n + i];
+    // dense arrays hold plain populations; the state holds them shifted
+    const double w = a == 0 ? 4.0 / 9.0 : (a <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+    if (to_dense) dense[a * n + i] = (T)((double)f[j] + w * d.rho_ref);
+    else f[j] = (T)((double)dense[a * n + i] - w * d.rho_ref);
 }
 
 __global__ void copy_kernel(uint4 *__restrict__ dst, const uint4 *__restrict__ src, size_t n16)
@@ -944,6 +984,15 @@ hipError_t launch_init(int prec, const InstDev *d_inst, int slab_rows, const lbm
     const unsigned grid = (unsigned)((nsites + 255) / 256);
     if (prec == LBM_FP64) init_kernel<double><<<grid, 256, 0, st>>>(d_inst, A);
     else init_kernel<float><<<grid, 256, 0, st>>>(d_inst, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_density(int prec, const InstDev *d_inst, const double *rho, long long nsites,
+                              hipStream_t st)
+{
+    const unsigned grid = (unsigned)((nsites + 255) / 256);
+    if (prec == LBM_FP64) init_density_kernel<double><<<grid, 256, 0, st>>>(d_inst, rho);
+    else init_density_kernel<float><<<grid, 256, 0, st>>>(d_inst, rho);
     return hipGetLastError();
 }
 

@@ -77,6 +77,7 @@ _SIGS = {
     "lbm_init_bubble": [ctypes.c_void_p, ctypes.POINTER(Bubble), ctypes.c_int, ctypes.c_int,
                         ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                         ctypes.c_double, ctypes.c_uint64],
+    "lbm_init_density": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double],
     "lbm_step": [ctypes.c_void_p, ctypes.c_int64],
     "lbm_step_timed": [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_float)],
     "lbm_macros": [ctypes.c_void_p] + [ctypes.c_void_p] * 4 + [ctypes.POINTER(Diag)],
@@ -239,6 +240,20 @@ class Sim:
         arr = _bubbles(bubbles)
         _check(lib().lbm_init_bubble(self.h, arr, len(bubbles), int(slab_rows), rho_l, rho_g, W,
                                      delta, noise_amp, int(seed)), "lbm_init_bubble")
+        return self
+
+    def init_density(self, rho, rho_l=None, rho_g=None):
+        """Rest state f_a = w_a rho from a (ny, nx) density field."""
+        if rho_l is None or rho_g is None:
+            g, l, _ = maxwell(self.params.T, self.params.a, self.params.b, self.params.R)
+            rho_l = l if rho_l is None else rho_l
+            rho_g = g if rho_g is None else rho_g
+        self.rho_l, self.rho_g = rho_l, rho_g
+        with torch.cuda.stream(self.stream):
+            r = torch.as_tensor(rho, dtype=torch.float64).to(self.device).contiguous()
+        assert r.shape == (self.ny, self.nx)
+        _check(lib().lbm_init_density(self.h, r.data_ptr(), rho_l, rho_g), "lbm_init_density")
+        self.stream.synchronize()
         return self
 
     def step(self, n=1):

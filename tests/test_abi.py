@@ -1,0 +1,82 @@
+"""The C ABI: the built library loads without a GPU, exports every function
+include/lbm.h declares, and its host-only helpers agree with the oracle's
+independent solvers."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from tests.conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(lbm_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_boundary_calls():
+    names = declared_functions()
+    for core in ("lbm_create", "lbm_init_bubble", "lbm_step", "lbm_macros", "lbm_destroy",
+                 "lbm_workspace_bytes", "lbm_batch_create", "lbm_batch_step"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = pytest.importorskip("paper_1605_01800_amd.lbm")
+    lib = L.lib()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding declares every one of them
+    assert set(declared_functions()) <= set(L._SIGS)
+
+
+def test_binding_structs_match_the_header_sizes():
+    L = pytest.importorskip("paper_1605_01800_amd.lbm")
+    assert ctypes.sizeof(L.Params) == 4 * 4 + 12 * 8
+    assert ctypes.sizeof(L.Bubble) == 24
+    assert ctypes.sizeof(L.Diag) == 8 + 3 * 8 + 2 * 4 + 16 * 8 + 8 + 8
+
+
+def test_host_critical_point_and_maxwell_agree_with_oracle(coexistence_table):
+    """liblbm's long-double solvers (equal pressure and chemical potential)
+    against the oracle's multiprecision equal-area solutions."""
+    L = pytest.importorskip("paper_1605_01800_amd.lbm")
+    from oracle import coexist
+    Tc, rc, pc = L.critical_point()
+    oTc, orc, opc = coexist.critical_point()
+    assert abs(Tc - oTc) / oTc < 1e-14 and abs(rc - orc) / orc < 1e-12 and abs(pc - opc) / opc < 1e-12
+    for tr, row in coexistence_table.items():
+        g, l, p0 = L.maxwell(row["T"])
+        mg, ml, mp0 = row["maxwell"]
+        assert abs(g - mg) / mg < 1e-9 and abs(l - ml) / ml < 1e-11 and abs(p0 - mp0) / mp0 < 1e-9
+
+
+def test_invalid_parameters_are_rejected_without_a_device():
+    L = pytest.importorskip("paper_1605_01800_amd.lbm")
+    lib = L.lib()
+    n = ctypes.c_size_t()
+    good = L.make_params(100, 50, T_over_Tc=0.7)
+    assert lib.lbm_workspace_bytes(ctypes.byref(good), ctypes.byref(n)) == 0 and n.value > 0
+    for field, val in (("nx", 0), ("ny", -3), ("walls_y", 2), ("precision", 7), ("G", 1.0),
+                       ("T", 0.0), ("s_nu", 2.0), ("s_e", 0.0), ("nx", 70000)):
+        p = L.make_params(100, 50, T_over_Tc=0.7)
+        setattr(p, field, val)
+        assert lib.lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == -1, field
+    big = L.make_params(65536, 65536, T_over_Tc=0.7)        # a plane of 16 GiB
+    assert lib.lbm_workspace_bytes(ctypes.byref(big), ctypes.byref(n)) == -1
+    assert L.maxwell.__doc__
+    with pytest.raises(L.LbmError):
+        L.maxwell(L.critical_point()[0] * 1.01)
+
+
+def test_workspace_grows_with_precision_and_grid():
+    L = pytest.importorskip("paper_1605_01800_amd.lbm")
+    a = L.workspace_bytes(L.make_params(256, 256, T_over_Tc=0.7, precision="fp32"))
+    b = L.workspace_bytes(L.make_params(256, 256, T_over_Tc=0.7, precision="fp64"))
+    c = L.workspace_bytes(L.make_params(512, 256, T_over_Tc=0.7, precision="fp32"))
+    assert 2 * 9 * 256 * 256 * 4 < a < b and a < c
+    assert L.tile_count(L.make_params(100, 37, T_over_Tc=0.7)) == 2 * 10

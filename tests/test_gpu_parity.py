@@ -31,16 +31,19 @@ def _variant(name):
     return L.variant_names().index(name)
 
 
-@pytest.mark.parametrize("variant", ["2pass-64x4", "fused-64x16", "fused-64x128"])
+@pytest.mark.parametrize("variant,shift", [("2pass-64x4", False), ("fused-64x16", False),
+                                           ("fused-64x128", False), ("2pass-64x8", True),
+                                           ("fused-64x32", True)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_mixed"])
 @pytest.mark.parametrize("nx,ny,walls", [(100, 37, False), (100, 37, True), (64, 8, False),
                                          (130, 5, True), (1, 6, False), (3, 1, True),
                                          (200, 131, True)])
-def test_single_step_from_random_state(prec, nx, ny, walls, variant):
+def test_single_step_from_random_state(prec, nx, ny, walls, variant, shift):
     """One step from a generic state on ragged grids (x not a multiple of 64,
     tiny and degenerate sizes, both boundary kinds), for the two-pass and the
-    fused kernels."""
-    print("case", prec, nx, ny, walls, variant, flush=True)
+    fused kernels, with populations stored plain (reference density 0) or
+    shifted by the rest equilibrium of the liquid density."""
+    print("case", prec, nx, ny, walls, variant, shift, flush=True)
     T = coexist.temperature(0.7)
     p = L.make_params(nx, ny, T=T, walls=walls, precision=prec, tau_nu=0.6)
     P = oracle_params(p)
@@ -48,6 +51,8 @@ def test_single_step_from_random_state(prec, nx, ny, walls, variant):
     f0 = inputs.random_populations(rho, seed=nx * 1000 + ny, amp=0.3)
     sim = L.Sim(p)
     sim.set_variant(_variant(variant))
+    if shift:
+        sim.init_density(rho)            # sets the shift reference to rho_l
     dt = sim.dtype
     sim.set_populations(to_device(f0, dt))
     start = to_oracle(sim.populations())          # the state as the device holds it
