@@ -206,7 +206,9 @@ void lbm_batch_destroy(void *batch);
 int lbm_variant_count(void);
 const char *lbm_variant_name(int variant);
 /* Selects the tile-shape variant a handle or a batch launches (results are
- * bitwise independent of it). */
+ * bitwise independent of it).  The paired variants ("fused2-*") need an even
+ * nx for every instance: LBM_EINVAL otherwise, also from lbm_batch_attach of
+ * an odd-nx instance to a batch using one; the autotuner skips them then. */
 int lbm_set_variant(void *handle, int variant);
 int lbm_batch_set_variant(void *batch, int variant);
 /* Times every variant on the batch's current instances with HIP events

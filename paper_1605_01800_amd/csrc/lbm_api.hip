@@ -173,6 +173,34 @@ struct Batch {
 
 hipStream_t stream_of(const Instance *h);
 
+template <typename T>
+void fill_consts(Consts<T> &c, const InstDev &d)
+{
+    c.RT = (T)d.RT;
+    c.a = (T)d.a;
+    c.b4 = (T)d.b4;
+    c.two_over_G = (T)d.two_over_G;
+    c.mG = (T)(-d.G);
+    c.rho_ref = (T)d.rho_ref;
+    c.s_e = (T)d.s_e;
+    c.s_z = (T)d.s_z;
+    c.s_q = (T)d.s_q;
+    c.s_nu = (T)d.s_nu;
+    c.h_e = (T)(1.0 - 0.5 * d.s_e);
+    c.h_z = (T)(1.0 - 0.5 * d.s_z);
+    c.h_q = (T)(1.0 - 0.5 * d.s_q);
+    c.h_nu = (T)(1.0 - 0.5 * d.s_nu);
+    c.li_e = (T)d.li_e;
+    c.li_z = (T)d.li_z;
+}
+
+// Refreshes the per-precision constant copies after a descriptor change.
+void refresh_consts(InstDev &d)
+{
+    fill_consts(d.cf, d);
+    fill_consts(d.cd, d);
+}
+
 void fill_desc(Instance *h)
 {
     const lbm_params &p = h->p;
@@ -203,14 +231,15 @@ void fill_desc(Instance *h)
     d.s_nu = p.s_nu;
     d.li_e = p.s_e * 0.75 * p.eps;
     d.li_z = p.s_zeta * 0.75 * p.eps;
+    refresh_consts(d);
 }
 
 void build_tiles(int inst_index, const lbm_params &p, int variant, std::vector<Tile> &out)
 {
-    const int rows = tile_rows(variant);
+    const int rows = tile_rows(variant), cols = tile_cols(variant);
     int k = 0;
     for (int y0 = 0; y0 < p.ny; y0 += rows)
-        for (int x0 = 0; x0 < p.nx; x0 += TILE_X) {
+        for (int x0 = 0; x0 < p.nx; x0 += cols) {
             Tile t;
             t.inst = inst_index;
             t.x0 = x0;
@@ -262,7 +291,9 @@ int enqueue_chunk(int prec, int variant, const InstDev *d_inst, int ninst, const
                   int ntiles, int K, hipStream_t st)
 {
     for (int s = 0; s < K; ++s) {
-        if (kVariants[variant].fused) {
+        if (kVariants[variant].fused == 2) {
+            TRYHIP(launch_fused2(prec, variant, d_inst, d_tiles, ntiles, s, st));
+        } else if (kVariants[variant].fused == 1) {
             TRYHIP(launch_fused(prec, variant, d_inst, d_tiles, ntiles, s, st));
         } else {
             TRYHIP(launch_psi_pass(prec, variant, d_inst, d_tiles, ntiles, s, st));
@@ -388,7 +419,12 @@ int batch_run(Batch *b, const std::vector<int64_t> &counts, bool timed, float *m
             for (int s = 0; s < K && rc == LBM_OK && fused; ++s) {
                 float t;
                 rc = hip_ok(hipEventRecord(e0, b->stream));
-                if (rc == LBM_OK) rc = hip_ok(launch_fused(b->precision, b->variant, b->d_descs, b->d_tiles, b->ntiles, s, b->stream));
+                if (rc == LBM_OK) {
+                    if (kVariants[b->variant].fused == 2)
+                        rc = hip_ok(launch_fused2(b->precision, b->variant, b->d_descs, b->d_tiles, b->ntiles, s, b->stream));
+                    else
+                        rc = hip_ok(launch_fused(b->precision, b->variant, b->d_descs, b->d_tiles, b->ntiles, s, b->stream));
+                }
                 if (rc == LBM_OK) rc = hip_ok(hipEventRecord(e1, b->stream));
                 if (rc == LBM_OK) rc = hip_ok(hipEventSynchronize(e1));
                 if (rc == LBM_OK) rc = hip_ok(hipEventElapsedTime(&t, e0, e1));
@@ -521,6 +557,7 @@ int lbm_init_bubble(void *handle, const lbm_bubble *b, int nb, int slab_rows, do
     d.rho_l = rho_l;
     d.rho_g = rho_g;
     d.rho_ref = storage_value(h->p.precision, rho_l);
+    refresh_consts(d);
     for (int k = 0; k < LBM_MAX_BUBBLES; ++k) {
         d.bx[k] = k < nbub ? b[k].x0 : 0.0;
         d.by[k] = k < nbub ? b[k].y0 : 0.0;
@@ -550,6 +587,7 @@ int lbm_init_density(void *handle, const void *d_rho, double rho_l, double rho_g
     d.rho_l = rho_l;
     d.rho_g = rho_g;
     d.rho_ref = storage_value(h->p.precision, rho_l);
+    refresh_consts(d);
     h->desc_dirty = true;
     if (h->batch) h->batch->dirty = true;
     TRY(sync_own(h));
@@ -773,6 +811,7 @@ int lbm_load(void *handle, const void *host_buf, size_t bytes)
     d.rho_l = hd.rho_l;
     d.rho_g = hd.rho_g;
     d.rho_ref = hd.rho_ref;
+    refresh_consts(d);
     for (int k = 0; k < LBM_MAX_BUBBLES; ++k) {
         h->bubbles[k] = hd.bubbles[k];
         d.bx[k] = k < hd.n_bubbles ? hd.bubbles[k].x0 : 0.0;
@@ -809,6 +848,7 @@ int lbm_set_variant(void *handle, int variant)
 {
     Instance *h = (Instance *)handle;
     if (!h || variant < 0 || variant >= kNumVariants) return LBM_EINVAL;
+    if (!variant_fits(variant, h->p.nx)) return LBM_EINVAL;
     if (h->variant != variant) {
         h->variant = variant;
         h->tiles_dirty = true;
@@ -858,6 +898,7 @@ int lbm_batch_attach(void *batch, void *handle)
     if (!b || !h) return LBM_EINVAL;
     if (h->batch) return LBM_ESTATE;
     if (h->p.precision != b->precision) return LBM_EINVAL;
+    if (!variant_fits(b->variant, h->p.nx)) return LBM_EINVAL;
     if ((int)b->members.size() >= b->max_inst) return LBM_ENOMEM;
     // order the instance's pending work before the batch's
     TRYHIP(hipStreamSynchronize(h->stream));
@@ -917,6 +958,8 @@ int lbm_batch_set_variant(void *batch, int variant)
 {
     Batch *b = (Batch *)batch;
     if (!b || variant < 0 || variant >= kNumVariants) return LBM_EINVAL;
+    for (Instance *h : b->members)
+        if (!variant_fits(variant, h->p.nx)) return LBM_EINVAL;
     if (b->variant != variant) {
         b->variant = variant;
         b->dirty = true;
@@ -936,6 +979,9 @@ int lbm_batch_autotune(void *batch, int reps, int *best_variant, float *ms_per_s
     float best_ms = INFINITY;
     int rc = LBM_OK;
     for (int v = 0; v < kNumVariants && rc == LBM_OK; ++v) {
+        bool fits = true;
+        for (Instance *h : b->members) fits = fits && variant_fits(v, h->p.nx);
+        if (!fits) continue;
         rc = lbm_batch_set_variant(b, v);
         if (rc == LBM_OK) rc = lbm_batch_step(b, std::min(reps, 8));     // warm-up and capture
         if (rc == LBM_OK) rc = hip_ok(hipEventRecord(e0, b->stream));

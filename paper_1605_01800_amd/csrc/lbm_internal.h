@@ -22,6 +22,17 @@ constexpr int MAX_CHUNK = 256;
 // mass, momentum x, momentum y, then one gas area per bubble.
 constexpr int N_PARTIAL = 3 + LBM_MAX_BUBBLES;
 
+// Per-instance constants in one precision, so that kernels read them as
+// scalars instead of converting binary64 values in every lane.
+template <typename T>
+struct Consts {
+    T RT, a, b4, two_over_G, mG;   // Eq. 15, Eq. 13 (2 / (G c^2)), -G of Eq. 7
+    T rho_ref;                     // population shift reference
+    T s_e, s_z, s_q, s_nu;         // rates of the relaxed moments (Eq. 2)
+    T h_e, h_z, h_q, h_nu;         // 1 - s/2
+    T li_e, li_z;                  // Li's term after (I - Lambda/2): s 0.75 eps
+};
+
 // Device-visible description of one instance.  The host keeps a mirror and
 // uploads it when it changes; kernels only read it, except the end-of-chunk
 // kernel, which folds the per-step wall-pressure slots.
@@ -51,6 +62,8 @@ struct InstDev {
     // g_a = f_a - w_a rho_ref (rho_ref representable in the storage precision)
     double rho_ref;
     double bx[LBM_MAX_BUBBLES], by[LBM_MAX_BUBBLES];
+    Consts<float> cf;
+    Consts<double> cd;
 };
 
 // One entry of the tile work-list.
@@ -64,7 +77,9 @@ struct Tile {
 // force+collide+stream pass over tiles of TILE_X x (ROW_GROUPS * rows) sites,
 // each thread taking `rows` rows.  Fused variants (fused == 1) launch one
 // kernel per step over strips of TILE_X x rows sites that rebuild psi for the
-// strip and its one-site ring on the fly.
+// strip and its one-site ring on the fly.  Paired fused variants (fused == 2)
+// do the same over strips of 2 * TILE_X x rows sites, two neighbouring sites
+// per lane with two-element loads and stores; they need an even nx.
 struct Variant {
     int fused;
     int rows;
@@ -78,6 +93,10 @@ inline int tile_rows(int variant)
     return kVariants[variant].fused ? kVariants[variant].rows : ROW_GROUPS * kVariants[variant].rows;
 }
 
+inline int tile_cols(int variant) { return kVariants[variant].fused == 2 ? 2 * TILE_X : TILE_X; }
+
+inline bool variant_fits(int variant, int nx) { return kVariants[variant].fused != 2 || nx % 2 == 0; }
+
 // Kernels, launched on a stream.  prec is an lbm_precision.
 hipError_t launch_psi_pass(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles,
                            int ntiles, int s, hipStream_t st);
@@ -85,6 +104,8 @@ hipError_t launch_collide_stream(int prec, int variant, const InstDev *d_inst, c
                                  int ntiles, int s, hipStream_t st);
 hipError_t launch_fused(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles, int ntiles,
                         int s, hipStream_t st);
+hipError_t launch_fused2(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles, int ntiles,
+                         int s, hipStream_t st);
 hipError_t launch_chunk_end(const InstDev *d_inst, int ninst, hipStream_t st);
 hipError_t launch_init(int prec, const InstDev *d_inst, int slab_rows, const lbm_bubble *b, int nb,
                        double rho_l, double rho_g, double W, double delta, double noise_amp,

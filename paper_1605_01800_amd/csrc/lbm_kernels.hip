@@ -25,8 +25,9 @@
 namespace lbm {
 
 const Variant kVariants[] = {
-    {0, 1, "2pass-64x4"},  {0, 2, "2pass-64x8"},  {0, 4, "2pass-64x16"}, {0, 8, "2pass-64x32"},
-    {1, 16, "fused-64x16"}, {1, 32, "fused-64x32"}, {1, 64, "fused-64x64"}, {1, 128, "fused-64x128"}};
+    {0, 1, "2pass-64x4"},    {0, 2, "2pass-64x8"},    {0, 4, "2pass-64x16"},   {0, 8, "2pass-64x32"},
+    {1, 16, "fused-64x16"},  {1, 32, "fused-64x32"},  {1, 64, "fused-64x64"},  {1, 128, "fused-64x128"},
+    {2, 16, "fused2-128x16"}, {2, 32, "fused2-128x32"}, {2, 64, "fused2-128x64"}};
 const int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 namespace {
@@ -608,6 +609,258 @@ __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict_
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// paired fused pass: the fused pass with two neighbouring sites per lane
+// ---------------------------------------------------------------------------
+// Same walk as fused_kernel over strips of 2 * TILE_X columns; lane l owns the
+// columns x0 + 2l and x0 + 2l + 1 and moves both with one two-element access
+// per population plane (a 64-wide wavefront reads 512 B of a plane at once),
+// which the memory system serves markedly faster than one element per lane.
+// Populations moving in x land on the neighbouring pair: the value entering a
+// pair from the left comes from the lane to the left (a lane shuffle), so every
+// store stays aligned; the one value that crosses a strip edge is stored on
+// its own by the edge lane.  nx must be even, so that a pair never straddles
+// the end of a row (the host enforces it).
+typedef float float_pair __attribute__((ext_vector_type(2)));
+typedef double double_pair __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct Pair;
+template <>
+struct Pair<float> {
+    using type = float_pair;
+};
+template <>
+struct Pair<double> {
+    using type = double_pair;
+};
+
+template <typename T>
+__device__ __forceinline__ typename Pair<T>::type ldp(gptr<const char> row_base, unsigned lane_off)
+{
+    return *(gptr<const typename Pair<T>::type>)(row_base + lane_off);
+}
+
+template <typename T>
+__device__ __forceinline__ void stp(gptr<char> row_base, unsigned lane_off, T a, T b)
+{
+    typename Pair<T>::type v;
+    v.x = a;
+    v.y = b;
+    *(gptr<typename Pair<T>::type>)(row_base + lane_off) = v;
+}
+
+// Lane-position facts of a pair (all offsets in bytes).
+struct PairLane {
+    unsigned xo;        // the pair's own first column
+    unsigned xo1;       // the pair's second column
+    unsigned east_ovf;  // where the last pair's right value goes moving east
+    unsigned west_ovf;  // where lane 0's left value goes moving west
+    bool valid;         // the pair holds lattice sites
+    bool first;         // lane 0
+    bool last;          // the strip's last valid pair
+};
+
+// Stores one direction's post-collision pair (v0 at column cx, v1 at cx + 1)
+// into `row`, shifted in x by shift = 0, +1 (east) or -1 (west).  All lanes
+// must call it together (it shuffles).
+template <typename T>
+__device__ __forceinline__ void store_pair(gptr<char> row, int shift, T v0, T v1, const PairLane &pl)
+{
+    if (shift == 0) {
+        if (pl.valid) stp<T>(row, pl.xo, v0, v1);
+    } else if (shift > 0) {
+        const T up = __shfl_up(v1, 1);            // right value of the pair to the left
+        if (pl.valid) {
+            if (pl.first) st<T>(row, pl.xo1, v0);
+            else stp<T>(row, pl.xo, up, v0);
+            if (pl.last) st<T>(row, pl.east_ovf, v1);
+        }
+    } else {
+        const T dn = __shfl_down(v0, 1);          // left value of the pair to the right
+        if (pl.valid) {
+            if (pl.last) st<T>(row, pl.xo, v1);
+            else stp<T>(row, pl.xo, v1, dn);
+            if (pl.first) st<T>(row, pl.west_ovf, v0);
+        }
+    }
+}
+
+template <typename T, bool EOS64, int H>
+__global__ __launch_bounds__(BLOCK) void fused2_kernel(const InstDev *__restrict__ insts,
+                                                       const Tile *__restrict__ tiles, int ntiles, int s)
+{
+    using V = typename Pair<T>::type;
+    constexpr int RING = 16;
+    constexpr int SW = 2 * TILE_X;
+    constexpr int LW = SW + 2;
+    constexpr int NLOAD = (H + 2 + ROW_GROUPS - 1) / ROW_GROUPS;
+    constexpr int NK = NLOAD + 2;
+    static_assert(H % ROW_GROUPS == 0, "strip height must be a multiple of the row groups");
+    __shared__ T ring[RING * LW];
+
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    if (t >= ntiles) return;
+    const Tile tl = tiles[t];
+    const InstDev &d = insts[tl.inst];
+    if (s >= d.n_chunk) return;
+    const int sb = src_buffer(d, s);
+    const gptr<const char> f = global_ptr<const char>(d.f[sb]);
+    const gptr<char> fo = global_ptr<char>(d.f[sb ^ 1]);
+    const unsigned long long PB = (unsigned long long)d.plane * sizeof(T);
+    const unsigned long long RB = (unsigned long long)d.pitch * sizeof(T);
+    const int nx = d.nx, ny = d.ny, walls = d.walls;
+    const int lane = threadIdx.x & (TILE_X - 1);
+    const int w = wave_index();
+    const int cx = tl.x0 + 2 * lane;                         // the pair's first column
+    const int last_cx = min(tl.x0 + SW, nx) - 2;
+    PairLane pl;
+    pl.valid = cx < nx;
+    pl.first = lane == 0;
+    pl.last = cx == last_cx;
+    pl.xo = (unsigned)cx * sizeof(T);
+    pl.xo1 = (unsigned)(cx + 1) * sizeof(T);
+    pl.east_ovf = (unsigned)((cx + 2) % nx) * sizeof(T);
+    pl.west_ovf = (unsigned)(tl.x0 == 0 ? nx - 1 : tl.x0 - 1) * sizeof(T);
+    const unsigned xlo = (unsigned)(pl.valid ? cx : cx % nx) * sizeof(T);   // pair loaded (wrapped)
+    const bool halo = lane < 2;
+    const int xh = lane == 0 ? (tl.x0 == 0 ? nx - 1 : tl.x0 - 1) : (tl.x0 + SW) % nx;
+    const unsigned xho = (unsigned)xh * sizeof(T);
+    const int hslot = lane == 0 ? 0 : LW - 1;
+    const int y_end = min(tl.y0 + H, ny);
+    const bool track = walls && (tl.y0 == 0 || tl.y0 + H >= ny);
+    const Rates<T> R = load_rates<T>(d);
+    const T mG = -(T)d.G;
+    const T rho_ref = (T)d.rho_ref;
+
+    bool bad = false;
+    double wmax = -INFINITY;
+    V fa[9], fb[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        fa[a].x = fa[a].y = T(0);
+        fb[a].x = fb[a].y = T(0);
+    }
+
+    for (int k = 0; k < NK; ++k) {
+        const int l = tl.y0 - 1 + ROW_GROUPS * k + w;
+        const bool do_load = k < NLOAD && l <= tl.y0 + H && l <= ny;
+        int mr = l;
+        if (walls) mr = mr < 0 ? 0 : (mr > ny - 1 ? ny - 1 : mr);
+        else mr = mr < 0 ? mr + ny : (mr >= ny ? mr - ny : mr);
+        const gptr<const char> rb = f + (unsigned long long)mr * RB;
+        V fn[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) fn[a].x = fn[a].y = T(0);
+        T dm_h = T(0);
+        if (do_load && halo) {
+            T fh[9];
+#pragma unroll
+            for (int a = 0; a < 9; ++a) fh[a] = ld<T>(rb + a * PB, xho);
+            dm_h = density<T>(fh);
+        }
+        if (do_load) {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) fn[a] = ldp<T>(rb + a * PB, xlo);
+        }
+        T *row = ring + ((l + 2 * RING) % RING) * LW;
+        if (do_load && halo) {
+            const T ph = pseudopotential<T, EOS64>(dm_h, d);
+            row[hslot] = ph;
+            bad |= !finite_value(ph);
+        }
+
+        // collide and push the row loaded two iterations ago
+        const int c = l - 2 * ROW_GROUPS;
+        if (k >= 2 && c >= tl.y0 && c < y_end) {
+            const T *rS = ring + ((c - 1 + 2 * RING) % RING) * LW;
+            const T *rC = ring + ((c + 2 * RING) % RING) * LW;
+            const T *rN = ring + ((c + 1 + 2 * RING) % RING) * LW;
+            T v0[9], v1[9];
+#pragma unroll
+            for (int a = 0; a < 9; ++a) {
+                v0[a] = fb[a].x;
+                v1[a] = fb[a].y;
+            }
+            T pc, Fx, Fy;
+            interaction_force<T>(rS, rC, rN, 2 * lane + 1, mG, pc, Fx, Fy);
+            collide_site<T>(v0, pc, Fx, Fy, rho_ref, R);
+            interaction_force<T>(rS, rC, rN, 2 * lane + 2, mG, pc, Fx, Fy);
+            collide_site<T>(v1, pc, Fx, Fy, rho_ref, R);
+
+            // Eq. 5 with halfway bounce-back; the row conditions are uniform
+            const bool top = (c == ny - 1), bot = (c == 0);
+            int yn = c + 1, ys = c - 1;
+            if (!walls) {
+                if (top) yn = 0;
+                if (bot) ys = ny - 1;
+            }
+            const gptr<char> r0 = fo + (unsigned long long)c * RB;
+            const gptr<char> rn = fo + (unsigned long long)yn * RB;
+            const gptr<char> rs = fo + (unsigned long long)ys * RB;
+            store_pair<T>(r0, 0, v0[0], v1[0], pl);
+            store_pair<T>(r0 + 1 * PB, +1, v0[1], v1[1], pl);
+            store_pair<T>(r0 + 3 * PB, -1, v0[3], v1[3], pl);
+            if (walls && top) {
+                store_pair<T>(r0 + 4 * PB, 0, v0[2], v1[2], pl);
+                store_pair<T>(r0 + 7 * PB, 0, v0[5], v1[5], pl);
+                store_pair<T>(r0 + 8 * PB, 0, v0[6], v1[6], pl);
+            } else {
+                store_pair<T>(rn + 2 * PB, 0, v0[2], v1[2], pl);
+                store_pair<T>(rn + 5 * PB, +1, v0[5], v1[5], pl);
+                store_pair<T>(rn + 6 * PB, -1, v0[6], v1[6], pl);
+            }
+            if (walls && bot) {
+                store_pair<T>(r0 + 2 * PB, 0, v0[4], v1[4], pl);
+                store_pair<T>(r0 + 5 * PB, 0, v0[7], v1[7], pl);
+                store_pair<T>(r0 + 6 * PB, 0, v0[8], v1[8], pl);
+            } else {
+                store_pair<T>(rs + 4 * PB, 0, v0[4], v1[4], pl);
+                store_pair<T>(rs + 7 * PB, -1, v0[7], v1[7], pl);
+                store_pair<T>(rs + 8 * PB, +1, v0[8], v1[8], pl);
+            }
+        }
+
+        // psi of the row loaded now
+        if (do_load) {
+            T e0[9], e1[9];
+#pragma unroll
+            for (int a = 0; a < 9; ++a) {
+                e0[a] = fn[a].x;
+                e1[a] = fn[a].y;
+            }
+            const T dm0 = density<T>(e0), dm1 = density<T>(e1);
+            const T p0 = pseudopotential<T, EOS64>(dm0, d);
+            const T p1 = pseudopotential<T, EOS64>(dm1, d);
+            row[2 * lane + 1] = p0;
+            row[2 * lane + 2] = p1;
+            bad |= !finite_value(p0) || !finite_value(p1);
+            if (track && (l == 0 || l == ny - 1) && l >= tl.y0 && l < y_end && pl.valid) {
+                wmax = fmax(wmax, eos_pressure<double>(d.rho_ref + (double)dm0, d.RT, d.a, d.b4));
+                wmax = fmax(wmax, eos_pressure<double>(d.rho_ref + (double)dm1, d.RT, d.a, d.b4));
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            fb[a] = fa[a];
+            fa[a] = fn[a];
+        }
+    }
+    if (bad) d.flag[0] = 1;
+    if (track) {
+        __shared__ double red[BLOCK];
+        red[threadIdx.x] = wmax;
+        __syncthreads();
+        for (int k2 = BLOCK / 2; k2 > 0; k2 >>= 1) {
+            if (threadIdx.x < k2) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + k2]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0 && red[0] > -INFINITY) atomicMax(&d.wall_keys[s], order_key(red[0]));
+    }
+}
+
 // ---------------------------------------------------------------------------
 // end of a chunk: fold the per-step wall maxima, advance step counter/parity
 // ---------------------------------------------------------------------------
@@ -905,6 +1158,19 @@ hipError_t fused_dispatch(int variant, const InstDev *di, const Tile *dt, int nt
     return hipGetLastError();
 }
 
+template <typename T, bool E64>
+hipError_t fused2_dispatch(int variant, const InstDev *di, const Tile *dt, int nt, int s, hipStream_t st)
+{
+    const dim3 grid(grid_for(nt)), block(BLOCK);
+    switch (kVariants[variant].rows) {
+    case 16: fused2_kernel<T, E64, 16><<<grid, block, 0, st>>>(di, dt, nt, s); break;
+    case 32: fused2_kernel<T, E64, 32><<<grid, block, 0, st>>>(di, dt, nt, s); break;
+    case 64: fused2_kernel<T, E64, 64><<<grid, block, 0, st>>>(di, dt, nt, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t macros_dispatch(int variant, const InstDev *di, const Tile *dt, int nt, void *rho,
                            void *ux, void *uy, double *p, hipStream_t st)
@@ -944,10 +1210,20 @@ hipError_t launch_fused(int prec, int variant, const InstDev *d_inst, const Tile
                         int s, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
-    if (!kVariants[variant].fused) return hipErrorInvalidValue;
+    if (kVariants[variant].fused != 1) return hipErrorInvalidValue;
     if (prec == LBM_FP64) return fused_dispatch<double, false>(variant, d_inst, d_tiles, ntiles, s, st);
     if (prec == LBM_FP32) return fused_dispatch<float, false>(variant, d_inst, d_tiles, ntiles, s, st);
     return fused_dispatch<float, true>(variant, d_inst, d_tiles, ntiles, s, st);
+}
+
+hipError_t launch_fused2(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles, int ntiles,
+                         int s, hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    if (kVariants[variant].fused != 2) return hipErrorInvalidValue;
+    if (prec == LBM_FP64) return fused2_dispatch<double, false>(variant, d_inst, d_tiles, ntiles, s, st);
+    if (prec == LBM_FP32) return fused2_dispatch<float, false>(variant, d_inst, d_tiles, ntiles, s, st);
+    return fused2_dispatch<float, true>(variant, d_inst, d_tiles, ntiles, s, st);
 }
 
 hipError_t launch_chunk_end(const InstDev *d_inst, int ninst, hipStream_t st)

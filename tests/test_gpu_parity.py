@@ -33,17 +33,20 @@ def _variant(name):
 
 @pytest.mark.parametrize("variant,shift", [("2pass-64x4", False), ("fused-64x16", False),
                                            ("fused-64x128", False), ("2pass-64x8", True),
-                                           ("fused-64x32", True)])
+                                           ("fused-64x32", True), ("fused2-128x16", False),
+                                           ("fused2-128x64", True)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_mixed"])
 @pytest.mark.parametrize("nx,ny,walls", [(100, 37, False), (100, 37, True), (64, 8, False),
                                          (130, 5, True), (1, 6, False), (3, 1, True),
-                                         (200, 131, True)])
+                                         (200, 131, True), (2, 3, False), (258, 9, True)])
 def test_single_step_from_random_state(prec, nx, ny, walls, variant, shift):
     """One step from a generic state on ragged grids (x not a multiple of 64,
     tiny and degenerate sizes, both boundary kinds), for the two-pass and the
     fused kernels, with populations stored plain (reference density 0) or
     shifted by the rest equilibrium of the liquid density."""
     print("case", prec, nx, ny, walls, variant, shift, flush=True)
+    if variant.startswith("fused2") and nx % 2:
+        pytest.skip("paired variants need an even nx")
     T = coexist.temperature(0.7)
     p = L.make_params(nx, ny, T=T, walls=walls, precision=prec, tau_nu=0.6)
     P = oracle_params(p)
@@ -66,20 +69,30 @@ def test_single_step_from_random_state(prec, nx, ny, walls, variant, shift):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_variants_are_bitwise_identical(prec):
-    """Every tile shape, two-pass or fused, gives the same bits (no halo or
-    ring race, no change of arithmetic order)."""
+    """Every tile shape of the two-pass and the fused kernels gives the same
+    bits (no halo or ring race, no change of arithmetic order).  The paired
+    kernels interleave two sites, and the compiler contracts a few products
+    differently there: they agree to rounding level (a race would not)."""
     T = coexist.temperature(0.7)
     p = L.make_params(150, 70, T=T, walls=True, precision=prec, tau_nu=0.8)
+    names = L.variant_names()
     outs = []
-    for v in range(len(L.variant_names())):
+    for v in range(len(names)):
         sim = L.Sim(p)
         sim.set_variant(v)
         sim.init_bubble([(74.5, 30.0, 14.0)], W=4.0)
         sim.step(40)
         outs.append(sim.populations().cpu())
         sim.close()
-    for o in outs[1:]:
-        assert torch.equal(o, outs[0])
+    ref = outs[0]
+    tol = 1e-14 if prec == "fp64" else 1e-6
+    for name, o in zip(names, outs):
+        err = float((o - ref).abs().max() / ref.abs().max())
+        print(name, err)
+        if name.startswith("fused2"):
+            assert err < tol, name
+        else:
+            assert torch.equal(o, ref), name
 
 
 def test_config1_fp64_matches_oracle_over_10000_steps():
@@ -130,7 +143,7 @@ def test_config1_fp32_within_1e4(prec):
     sim.close()
 
 
-@pytest.mark.parametrize("variant", ["2pass-64x8", "fused-64x32"])
+@pytest.mark.parametrize("variant", ["2pass-64x8", "fused-64x32", "fused2-128x32"])
 def test_walls_collapse_fp64_matches_oracle(variant):
     """Wall-bounded collapse set-up (Section 4.1): liquid at rho_l (1 + delta),
     seeded noise, halfway bounce-back at both walls."""
@@ -172,15 +185,16 @@ def test_macros_match_oracle_fields():
     sim.close()
 
 
-@pytest.mark.parametrize("variant", ["2pass-64x4", "fused-64x64"])
+@pytest.mark.parametrize("variant", ["2pass-64x4", "fused-64x64", "fused2-128x32"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_batch_equals_alone_bitwise(prec, variant):
     """Uneven grids stepped together give the bits of each stepped alone, also
     with different step counts per instance."""
     T6, T8 = coexist.temperature(0.6), coexist.temperature(0.8)
+    nx3 = 78 if variant.startswith("fused2") else 77
     specs = [(L.make_params(64, 64, T=T8, precision=prec), [(31.5, 31.5, 12.0)]),
              (L.make_params(200, 90, T=T6, walls=True, precision=prec, tau_nu=0.8), [(99.5, 30.0, 20.0)]),
-             (L.make_params(77, 129, T=T8, precision=prec, tau_nu=0.51), [(38.0, 64.0, 15.0)])]
+             (L.make_params(nx3, 129, T=T8, precision=prec, tau_nu=0.51), [(38.0, 64.0, 15.0)])]
     counts = [300, 173, 256]
     alone = []
     v = _variant(variant)
@@ -202,6 +216,14 @@ def test_batch_equals_alone_bitwise(prec, variant):
         assert s.diag()["step"] == n
         assert torch.equal(s.populations().cpu(), a)
     batch.close()
+
+
+def test_paired_variant_rejects_odd_nx():
+    p = L.make_params(77, 20, T_over_Tc=0.7, precision="fp32")
+    s = L.Sim(p)
+    with pytest.raises(L.LbmError):
+        s.set_variant(_variant("fused2-128x16"))
+    s.close()
 
 
 def test_checkpoint_roundtrip_is_bitwise():
@@ -241,7 +263,7 @@ def test_nonfinite_state_latches_and_refuses_to_step():
     sim.close()
 
 
-@pytest.mark.parametrize("variant", ["2pass-64x4", "fused-64x16"])
+@pytest.mark.parametrize("variant", ["2pass-64x4", "fused-64x16", "fused2-128x16"])
 def test_wall_pressure_peak_matches_oracle(variant):
     T = coexist.temperature(0.6)
     rg, rl, _ = coexist.maxwell(T)
