@@ -54,16 +54,46 @@ __device__ __forceinline__ gptr<T> global_ptr(void *p)
 // when an instance is created).  Written this way the loads and stores take
 // the scalar-base + 32-bit-offset form and all nine planes share one offset
 // register, instead of costing two address registers per access.
+//
+// The compiler tends to fold the scalar row offset into a per-lane 64-bit
+// address instead (one extra vector add per access); passing the row base
+// through an empty register-only asm statement that keeps it in scalar
+// registers prevents that.  Callers guarantee that row_base is the same in
+// every lane of the wavefront.
+template <typename P>
+__device__ __forceinline__ P scalar_base(P p)
+{
+    asm("" : "+s"(p));
+    return p;
+}
+
+// Likewise the 32-bit lane offset is passed through an empty asm statement at
+// every use, so that its widening to 64 bits stays next to the access (where
+// it folds into the addressing mode) rather than being hoisted out as a
+// 64-bit register pair.
+__device__ __forceinline__ unsigned lane_offset(unsigned o)
+{
+    asm("" : "+v"(o));
+    return o;
+}
+
 template <typename T>
 __device__ __forceinline__ T ld(gptr<const char> row_base, unsigned lane_off)
 {
-    return *(gptr<const T>)(row_base + lane_off);
+    return *(gptr<const T>)(scalar_base(row_base) + lane_offset(lane_off));
 }
 
 template <typename T>
 __device__ __forceinline__ void st(gptr<char> row_base, unsigned lane_off, T v)
 {
-    *(gptr<T>)(row_base + lane_off) = v;
+    *(gptr<T>)(scalar_base(row_base) + lane_offset(lane_off)) = v;
+}
+
+// Load whose address differs across the wavefront.
+template <typename T>
+__device__ __forceinline__ T ld_lane(gptr<const char> base, unsigned long long off)
+{
+    return *(gptr<const T>)(base + off);
 }
 
 // Index of the calling thread's wavefront, as a scalar.
@@ -129,6 +159,32 @@ __device__ __forceinline__ T density(const T v[9])
     return (((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]))) + v[8];
 }
 
+// 1/x and sqrt(x).  In binary64 correctly rounded.  In binary32 the hardware
+// instructions (at most one unit in the last place off) replace the longer
+// correctly rounded sequences: none of these quotients enters a conserved
+// moment (div9 and div6 handle those), so the extra error is unbiased noise
+// well below the binary32 path's own rounding.
+template <typename T>
+__device__ __forceinline__ T recip(T x)
+{
+    return T(1) / x;
+}
+template <>
+__device__ __forceinline__ float recip<float>(float x)
+{
+    return __builtin_amdgcn_rcpf(x);
+}
+template <typename T>
+__device__ __forceinline__ T root(T x)
+{
+    return sqrt(x);
+}
+template <>
+__device__ __forceinline__ float root<float>(float x)
+{
+    return __builtin_amdgcn_sqrtf(x);
+}
+
 // Carnahan-Starling pressure, Eq. 15, with eta = (b/4) rho.
 template <typename T>
 __device__ __forceinline__ T eos_pressure(T rho, T RT, T a, T b4)
@@ -136,7 +192,21 @@ __device__ __forceinline__ T eos_pressure(T rho, T RT, T a, T b4)
     const T eta = b4 * rho;
     const T om = T(1) - eta;
     const T num = T(1) + eta * (T(1) + eta * (T(1) - eta));
-    return rho * RT * num / (om * om * om) - a * rho * rho;
+    return rho * RT * num * recip(om * om * om) - a * rho * rho;
+}
+
+// The instance constants in the working precision.
+template <typename T>
+__device__ __forceinline__ const Consts<T> &consts(const InstDev &d);
+template <>
+__device__ __forceinline__ const Consts<float> &consts<float>(const InstDev &d)
+{
+    return d.cf;
+}
+template <>
+__device__ __forceinline__ const Consts<double> &consts<double>(const InstDev &d)
+{
+    return d.cd;
 }
 
 // Pseudopotential, Eq. 13 with c = 1 and c_s^2 = 1/3, of a site whose shifted
@@ -150,9 +220,10 @@ __device__ __forceinline__ T pseudopotential(T dm, const InstDev &d)
         const double p = eos_pressure<double>(r, d.RT, d.a, d.b4);
         return (T)sqrt((p - r * (1.0 / 3.0)) * d.two_over_G);
     } else {
-        const T rho = (T)d.rho_ref + dm;
-        const T p = eos_pressure<T>(rho, (T)d.RT, (T)d.a, (T)d.b4);
-        return sqrt((p - rho * T(1.0 / 3.0)) * (T)d.two_over_G);
+        const Consts<T> &c = consts<T>(d);
+        const T rho = c.rho_ref + dm;
+        const T p = eos_pressure<T>(rho, c.RT, c.a, c.b4);
+        return root((p - rho * T(1.0 / 3.0)) * c.two_over_G);
     }
 }
 
@@ -235,24 +306,6 @@ __global__ __launch_bounds__(BLOCK) void psi_pass_kernel(const InstDev *__restri
 // ---------------------------------------------------------------------------
 // collision of one site (Eqs. 6, 4, 14, 3 and f* = M^-1 m*)
 // ---------------------------------------------------------------------------
-template <typename T>
-struct Rates {
-    T s_e, s_z, s_q, s_nu;        // rates of the relaxed moments
-    T h_e, h_z, h_q, h_nu;        // 1 - s/2
-    T li_e, li_z;                 // s_e 0.75 eps, s_zeta 0.75 eps
-};
-
-template <typename T>
-__device__ __forceinline__ Rates<T> load_rates(const InstDev &d)
-{
-    Rates<T> r;
-    r.s_e = (T)d.s_e; r.s_z = (T)d.s_z; r.s_q = (T)d.s_q; r.s_nu = (T)d.s_nu;
-    r.h_e = (T)(1.0 - 0.5 * d.s_e); r.h_z = (T)(1.0 - 0.5 * d.s_z);
-    r.h_q = (T)(1.0 - 0.5 * d.s_q); r.h_nu = (T)(1.0 - 0.5 * d.s_nu);
-    r.li_e = (T)d.li_e; r.li_z = (T)d.li_z;
-    return r;
-}
-
 // f: shifted post-streaming populations g_a = f_a - w_a rho_ref of the site
 // (in), shifted post-collision populations (out).  psi_c: psi at the site;
 // Fx, Fy: force of Eq. 7.  The moments of g differ from those of f only in the
@@ -260,13 +313,13 @@ __device__ __forceinline__ Rates<T> load_rates(const InstDev &d)
 // moments), so every relaxation below is the one of Eq. 3 with those three
 // rows and their equilibria shifted alike.
 template <typename T>
-__device__ __forceinline__ void collide_site(T f[9], T psi_c, T Fx, T Fy, T rho_ref, const Rates<T> &R)
+__device__ __forceinline__ void collide_site(T f[9], T psi_c, T Fx, T Fy, const Consts<T> &R)
 {
     const T dm = density<T>(f);                 // rho - rho_ref
-    const T rho = rho_ref + dm;
+    const T rho = R.rho_ref + dm;
     const T jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
     const T jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-    const T inv_rho = T(1) / rho;
+    const T inv_rho = recip(rho);
     // Eq. 6 with delta_t = 1
     const T vx = (jx + T(0.5) * Fx) * inv_rho;
     const T vy = (jy + T(0.5) * Fy) * inv_rho;
@@ -294,7 +347,7 @@ __device__ __forceinline__ void collide_site(T f[9], T psi_c, T Fx, T Fy, T rho_
     // (I - Lambda/2) S with S of Eq. 14; for the e and zeta rows
     // (1 - s/2) / (tau - 1/2) = s, so Li's term enters as s 0.75 eps |F|^2 / psi^2.
     const T vF = vx * Fx + vy * Fy;
-    const T li = (Fx * Fx + Fy * Fy) / (psi_c * psi_c);
+    const T li = (Fx * Fx + Fy * Fy) * recip(psi_c * psi_c);
     const T q1 = R.h_e * T(6) * vF + R.li_e * li;
     const T q2 = -R.h_z * T(6) * vF - R.li_z * li;
     const T q4 = -R.h_q * Fx;
@@ -442,11 +495,11 @@ __global__ __launch_bounds__(BLOCK) void collide_stream_kernel(const InstDev *__
             gy %= ny;
             if (gy < 0) gy += ny;
         }
-        sp[k] = ld<T>(psi + (unsigned long long)gy * RB, (unsigned)gx * sizeof(T));
+        sp[k] = ld_lane<T>(psi, (unsigned long long)gy * RB + (unsigned)gx * sizeof(T));
     }
     __syncthreads();
 
-    const Rates<T> R = load_rates<T>(d);
+    const Consts<T> &R = consts<T>(d);
     const int lx = threadIdx.x & (TILE_X - 1);
     const int g = wave_index();
     const int x = tl.x0 + lx;
@@ -466,9 +519,9 @@ __global__ __launch_bounds__(BLOCK) void collide_stream_kernel(const InstDev *__
         for (int a = 0; a < 9; ++a) v[a] = ld<T>(rb + a * PB, xo);
 
         T pc, Fx, Fy;
-        interaction_force<T>(sp + ly * LW, sp + (ly + 1) * LW, sp + (ly + 2) * LW, lx + 1, -(T)d.G, pc,
+        interaction_force<T>(sp + ly * LW, sp + (ly + 1) * LW, sp + (ly + 2) * LW, lx + 1, R.mG, pc,
                              Fx, Fy);
-        collide_site<T>(v, pc, Fx, Fy, (T)d.rho_ref, R);
+        collide_site<T>(v, pc, Fx, Fy, R);
         push_store<T>(fo, PB, v, xo, xeo, xwo, y, ny, RB, d.walls);
     }
 }
@@ -527,8 +580,8 @@ __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict_
     const unsigned xwo = (unsigned)((x == 0) ? nx - 1 : x - 1) * sizeof(T);
     const int y_end = min(tl.y0 + H, ny);                     // rows collided: [y0, y_end)
     const bool track = walls && (tl.y0 == 0 || tl.y0 + H >= ny);
-    const Rates<T> R = load_rates<T>(d);
-    const T mG = -(T)d.G;
+    const Consts<T> &R = consts<T>(d);
+    const T mG = R.mG;
 
     bool bad = false;
     double wmax = -INFINITY;
@@ -536,6 +589,9 @@ __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict_
 #pragma unroll
     for (int a = 0; a < 9; ++a) fa[a] = fb[a] = T(0);
 
+    // Unrolled by three so that the rotation of the three row buffers
+    // (new -> one ago -> two ago) becomes register renaming, not moves.
+#pragma unroll 3
     for (int k = 0; k < NK; ++k) {
         const int l = tl.y0 - 1 + ROW_GROUPS * k + w;         // row loaded now
         const bool do_load = k < NLOAD && l <= tl.y0 + H && l <= ny;
@@ -576,7 +632,7 @@ __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict_
             const T *rN = ring + ((c + 1 + 2 * RING) % RING) * LW;
             T pc, Fx, Fy;
             interaction_force<T>(rS, rC, rN, lane + 1, mG, pc, Fx, Fy);
-            collide_site<T>(fb, pc, Fx, Fy, (T)d.rho_ref, R);
+            collide_site<T>(fb, pc, Fx, Fy, R);
             push_store<T>(fo, PB, fb, xo, xeo, xwo, c, ny, RB, walls);
         }
 
@@ -639,7 +695,7 @@ struct Pair<double> {
 template <typename T>
 __device__ __forceinline__ typename Pair<T>::type ldp(gptr<const char> row_base, unsigned lane_off)
 {
-    return *(gptr<const typename Pair<T>::type>)(row_base + lane_off);
+    return *(gptr<const typename Pair<T>::type>)(scalar_base(row_base) + lane_offset(lane_off));
 }
 
 template <typename T>
@@ -648,7 +704,7 @@ __device__ __forceinline__ void stp(gptr<char> row_base, unsigned lane_off, T a,
     typename Pair<T>::type v;
     v.x = a;
     v.y = b;
-    *(gptr<typename Pair<T>::type>)(row_base + lane_off) = v;
+    *(gptr<typename Pair<T>::type>)(scalar_base(row_base) + lane_offset(lane_off)) = v;
 }
 
 // Lane-position facts of a pair (all offsets in bytes).
@@ -730,9 +786,8 @@ __global__ __launch_bounds__(BLOCK) void fused2_kernel(const InstDev *__restrict
     const int hslot = lane == 0 ? 0 : LW - 1;
     const int y_end = min(tl.y0 + H, ny);
     const bool track = walls && (tl.y0 == 0 || tl.y0 + H >= ny);
-    const Rates<T> R = load_rates<T>(d);
-    const T mG = -(T)d.G;
-    const T rho_ref = (T)d.rho_ref;
+    const Consts<T> &R = consts<T>(d);
+    const T mG = R.mG;
 
     bool bad = false;
     double wmax = -INFINITY;
@@ -743,6 +798,9 @@ __global__ __launch_bounds__(BLOCK) void fused2_kernel(const InstDev *__restrict
         fb[a].x = fb[a].y = T(0);
     }
 
+    // Unrolled by three so that the rotation of the three row buffers
+    // (new -> one ago -> two ago) becomes register renaming, not moves.
+#pragma unroll 3
     for (int k = 0; k < NK; ++k) {
         const int l = tl.y0 - 1 + ROW_GROUPS * k + w;
         const bool do_load = k < NLOAD && l <= tl.y0 + H && l <= ny;
@@ -785,9 +843,9 @@ __global__ __launch_bounds__(BLOCK) void fused2_kernel(const InstDev *__restrict
             }
             T pc, Fx, Fy;
             interaction_force<T>(rS, rC, rN, 2 * lane + 1, mG, pc, Fx, Fy);
-            collide_site<T>(v0, pc, Fx, Fy, rho_ref, R);
+            collide_site<T>(v0, pc, Fx, Fy, R);
             interaction_force<T>(rS, rC, rN, 2 * lane + 2, mG, pc, Fx, Fy);
-            collide_site<T>(v1, pc, Fx, Fy, rho_ref, R);
+            collide_site<T>(v1, pc, Fx, Fy, R);
 
             // Eq. 5 with halfway bounce-back; the row conditions are uniform
             const bool top = (c == ny - 1), bot = (c == 0);
@@ -1010,7 +1068,7 @@ __global__ __launch_bounds__(BLOCK) void macros_kernel(const InstDev *__restrict
 #pragma unroll
         for (int a = 0; a < 9; ++a) v[a] = f[a * P + i];
         const T dm = density<T>(v);
-        const T rho = (T)d.rho_ref + dm;
+        const T rho = consts<T>(d).rho_ref + dm;
         const T jx = (v[1] - v[3]) + (v[5] - v[6]) + (v[8] - v[7]);
         const T jy = (v[2] - v[4]) + (v[5] + v[6]) - (v[7] + v[8]);
         auto ps = [&](int dx, int dy) -> T {
@@ -1026,7 +1084,7 @@ __global__ __launch_bounds__(BLOCK) void macros_kernel(const InstDev *__restrict
                      T(1.0 / 12.0) * ((ps(1, 1) - ps(-1, 1)) + (ps(1, -1) - ps(-1, -1)));
         const T gy = T(1.0 / 3.0) * (ps(0, 1) - ps(0, -1)) +
                      T(1.0 / 12.0) * ((ps(1, 1) + ps(-1, 1)) - (ps(1, -1) + ps(-1, -1)));
-        const T mG = -(T)d.G;
+        const T mG = consts<T>(d).mG;
         const T Fx = mG * pc * gx, Fy = mG * pc * gy;
         const T mx = jx + T(0.5) * Fx, my = jy + T(0.5) * Fy;
         const long long o = (long long)y * nx + x;
