@@ -437,8 +437,9 @@ def main():
     ms_psi, ms_col = batch.step_timed(nk)
     if fused:
         t_dom = ms / args.steps
-        dominant = ("fused_kernel", t_dom, BYTES_FUSED[es])
-        kernels = {"fused_kernel": {"ms_region_avg": t_dom, "ms_event_pair_avg": ms_col / nk,
+        kname = "fused2_kernel" if vname.startswith("fused2") else "fused_kernel"
+        dominant = (kname, t_dom, BYTES_FUSED[es])
+        kernels = {kname: {"ms_region_avg": t_dom, "ms_event_pair_avg": ms_col / nk,
                                     "bytes_per_site": BYTES_FUSED[es],
                                     "GB_s": round(BYTES_FUSED[es] * sites / (t_dom * 1e-3) / 1e9, 1)}}
     else:

@@ -205,15 +205,19 @@ void lbm_batch_destroy(void *batch);
 /* Number of tile-shape variants and a short name for each. */
 int lbm_variant_count(void);
 const char *lbm_variant_name(int variant);
-/* Selects the tile-shape variant a handle or a batch launches (results are
- * bitwise independent of it).  The paired variants ("fused2-*") need an even
+/* Selects the tile-shape variant a handle or a batch launches.  Results are
+ * bitwise the same for every variant except the paired ones ("fused2-*"),
+ * whose compiler contracts a few products differently (last-bit differences,
+ * within 1e-14 relative in binary64 per step).  The paired variants need an even
  * nx for every instance: LBM_EINVAL otherwise, also from lbm_batch_attach of
  * an odd-nx instance to a batch using one; the autotuner skips them then. */
 int lbm_set_variant(void *handle, int variant);
 int lbm_batch_set_variant(void *batch, int variant);
-/* Times every variant on the batch's current instances with HIP events
- * (reps steps each, state restored afterwards is NOT guaranteed: call before
- * initialising or on throwaway state), selects the fastest and returns it. */
+/* Times every variant on the batch's current instances with HIP events, in
+ * three rounds of min(reps, 8) warm-up steps and reps timed steps each, scores
+ * each variant by its fastest round, selects the best and returns it with its
+ * time per step.  It advances the instances' state (call it on throwaway
+ * state or before initialising). */
 int lbm_batch_autotune(void *batch, int reps, int *best_variant, float *ms_per_step);
 /* Runs n steps of the batch with a HIP event pair around every kernel launch
  * and returns the summed device time per kernel kind: ms[0] density/psi pass,

@@ -531,20 +531,47 @@ __global__ __launch_bounds__(BLOCK) void collide_stream_kernel(const InstDev *__
 // ---------------------------------------------------------------------------
 // A block owns a strip of TILE_X columns and H rows.  Its four wavefronts walk
 // down the strip together, wavefront w taking rows y0 - 1 + 4k + w at
-// iteration k: each loads the nine populations of its row (plus, in lanes 0
-// and 1, of the two columns left and right of the strip), forms rho and psi
-// (Eqs. 15, 13) and writes psi into a 16-row ring in LDS.  The row it loaded
-// two iterations earlier then has psi above and below it in the ring, and is
-// collided from the populations kept in registers (Eqs. 7, 6, 4, 14, 3) and
-// pushed to the other buffer (Eq. 5).  Every population is read from memory
-// once per step (the one-row and one-column rings are re-read by the
-// neighbouring strips), and psi never leaves LDS.
+// iteration k: each forms rho and psi (Eqs. 15, 13) of its row from the nine
+// populations loaded during the previous iteration and writes psi into a
+// 16-row ring in LDS.  The row it handled two iterations earlier then has psi
+// above and below it in the ring, and is collided from the populations kept
+// in registers (Eqs. 7, 6, 4, 14, 3) and pushed to the other buffer (Eq. 5).
+// Every population is read from memory once per step (the one-row and
+// one-column rings are re-read by the neighbouring strips), and psi never
+// leaves LDS.
+//
+// The loads of a row are issued one iteration before the row is used, so each
+// wavefront keeps the next row's loads in flight while it works; the
+// collision's stores and the barrier no longer wait behind them.  The two ring
+// columns left and right of the strip are loaded one population per lane
+// (lanes 0-8 and 16-24) and summed across lanes.
 //
 // Ring hazards: in iteration k the block writes psi of rows y0-1+4k .. y0+2+4k
 // and reads rows y0+4k-10 .. y0+4k-5, all written before the previous
 // barrier; the two sets are 4 to 12 rows apart, so with 16 slots no slot is
 // written while another wavefront reads it, and one barrier per iteration
 // suffices.
+
+// Lanes b .. b+8 (b = 0 or 16) hold populations 0..8 of one ring column;
+// returns in lane b the column's rho - rho_ref, summed in the order of
+// density().  Every lane of the wavefront must call it.
+template <typename T>
+__device__ __forceinline__ T halo_density(T v)
+{
+    const T s1 = v + __shfl_down(v, 1);       // lane b + 2i: v2i + v2i+1
+    const T s2 = s1 + __shfl_down(s1, 2);     // lane b + 4i: pairs of pairs
+    const T s3 = s2 + __shfl_down(s2, 4);     // lane b: v0 + ... + v7
+    return s3 + __shfl_down(v, 8);
+}
+
+// Memory row of lattice row l (ghost rows -1 and ny mirror at walls, wrap
+// otherwise).
+__device__ __forceinline__ int memory_row(int l, int ny, int walls)
+{
+    if (walls) return l < 0 ? 0 : (l > ny - 1 ? ny - 1 : l);
+    return l < 0 ? l + ny : (l >= ny ? l - ny : l);
+}
+
 template <typename T, bool EOS64, int H>
 __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict__ insts,
                                                       const Tile *__restrict__ tiles, int ntiles, int s)
@@ -571,13 +598,16 @@ __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict_
     const int w = wave_index();
     const int x = tl.x0 + lane;
     const int xl = x < nx ? x : x % nx;                       // column this lane loads
-    const bool halo = lane < 2;                               // lanes that also load a ring column
-    const int xh = lane == 0 ? (tl.x0 == 0 ? nx - 1 : tl.x0 - 1) : (tl.x0 + TILE_X) % nx;
-    const int hslot = lane == 0 ? 0 : LW - 1;
     const unsigned xo = (unsigned)x * sizeof(T), xlo = (unsigned)xl * sizeof(T);
-    const unsigned xho = (unsigned)xh * sizeof(T);
     const unsigned xeo = (unsigned)((x + 1 >= nx) ? 0 : x + 1) * sizeof(T);
     const unsigned xwo = (unsigned)((x == 0) ? nx - 1 : x - 1) * sizeof(T);
+    // ring columns: lane 16 c + a (a < 9) loads population a of column c
+    const int hp = lane & 15;
+    const bool hlane = lane < 32 && hp < 9;
+    const int hcol = lane < 16 ? (tl.x0 == 0 ? nx - 1 : tl.x0 - 1) : (tl.x0 + TILE_X) % nx;
+    const unsigned long long hoff = (unsigned long long)(hlane ? hp : 0) * PB + (unsigned)hcol * sizeof(T);
+    const bool hroot = lane == 0 || lane == 16;
+    const int hslot = lane == 0 ? 0 : LW - 1;
     const int y_end = min(tl.y0 + H, ny);                     // rows collided: [y0, y_end)
     const bool track = walls && (tl.y0 == 0 || tl.y0 + H >= ny);
     const Consts<T> &R = consts<T>(d);
@@ -585,46 +615,46 @@ __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict_
 
     bool bad = false;
     double wmax = -INFINITY;
-    T fa[9], fb[9];                                           // rows loaded 1 and 2 iterations ago
+    // rows of iterations k (fn), k - 1 (fa) and k - 2 (fb); hn: ring column
+    // population of row k
+    T fn[9], fa[9], fb[9], hn = T(0);
 #pragma unroll
-    for (int a = 0; a < 9; ++a) fa[a] = fb[a] = T(0);
+    for (int a = 0; a < 9; ++a) fn[a] = fa[a] = fb[a] = T(0);
 
-    // Unrolled by three so that the rotation of the three row buffers
-    // (new -> one ago -> two ago) becomes register renaming, not moves.
-#pragma unroll 3
+    auto row_loaded = [&](int k, int l) { return k < NLOAD && l <= tl.y0 + H && l <= ny; };
+    auto load_row = [&](int k, T v[9], T &h) {
+        const int l = tl.y0 - 1 + ROW_GROUPS * k + w;
+        if (row_loaded(k, l)) {
+            const gptr<const char> rb = f + (unsigned long long)memory_row(l, ny, walls) * RB;
+            if (hlane) h = ld_lane<T>(rb, hoff);
+#pragma unroll
+            for (int a = 0; a < 9; ++a) v[a] = ld<T>(rb + a * PB, xlo);
+        }
+    };
+    load_row(0, fn, hn);
+
+    // Unrolled by four so that the rotation of the four row buffers
+    // (next -> now -> one ago -> two ago) becomes register renaming.
+#pragma unroll 4
     for (int k = 0; k < NK; ++k) {
-        const int l = tl.y0 - 1 + ROW_GROUPS * k + w;         // row loaded now
-        const bool do_load = k < NLOAD && l <= tl.y0 + H && l <= ny;
-        int mr = l;                                           // memory row (ghost rows mirror or wrap)
-        if (walls) mr = mr < 0 ? 0 : (mr > ny - 1 ? ny - 1 : mr);
-        else mr = mr < 0 ? mr + ny : (mr >= ny ? mr - ny : mr);
-        // Loads of the new row are issued first and stay in flight while the
-        // row loaded two iterations ago is collided.  The ring-column loads
-        // (lanes 0 and 1) go out before them and are reduced to psi first, so
-        // their registers are free during the collision.
-        const gptr<const char> rb = f + (unsigned long long)mr * RB;
-        T fn[9];
+        const int l = tl.y0 - 1 + ROW_GROUPS * k + w;         // row handled now
+        const bool have = row_loaded(k, l);
+        T fq[9], hq = T(0);
 #pragma unroll
-        for (int a = 0; a < 9; ++a) fn[a] = T(0);
-        T dm_h = T(0);
-        if (do_load && halo) {
-            T fh[9];
-#pragma unroll
-            for (int a = 0; a < 9; ++a) fh[a] = ld<T>(rb + a * PB, xho);
-            dm_h = density<T>(fh);
-        }
-        if (do_load) {
-#pragma unroll
-            for (int a = 0; a < 9; ++a) fn[a] = ld<T>(rb + a * PB, xlo);
-        }
+        for (int a = 0; a < 9; ++a) fq[a] = T(0);
+        load_row(k + 1, fq, hq);                              // in flight until the next iteration
+
         T *row = ring + ((l + 2 * RING) % RING) * LW;
-        if (do_load && halo) {
-            const T ph = pseudopotential<T, EOS64>(dm_h, d);
-            row[hslot] = ph;
-            bad |= !finite_value(ph);
+        if (have) {
+            const T dm_h = halo_density<T>(hn);
+            if (hroot) {
+                const T ph = pseudopotential<T, EOS64>(dm_h, d);
+                row[hslot] = ph;
+                bad |= !finite_value(ph);
+            }
         }
 
-        // collide the row loaded two iterations ago
+        // collide the row handled two iterations ago
         const int c = l - 2 * ROW_GROUPS;
         if (k >= 2 && c >= tl.y0 && c < y_end && x < nx) {
             const T *rS = ring + ((c - 1 + 2 * RING) % RING) * LW;
@@ -636,8 +666,8 @@ __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict_
             push_store<T>(fo, PB, fb, xo, xeo, xwo, c, ny, RB, walls);
         }
 
-        // psi of the row loaded now
-        if (do_load) {
+        // psi of the row handled now
+        if (have) {
             const T dm = density<T>(fn);
             const T ps = pseudopotential<T, EOS64>(dm, d);
             row[lane + 1] = ps;
@@ -650,7 +680,9 @@ __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict_
         for (int a = 0; a < 9; ++a) {
             fb[a] = fa[a];
             fa[a] = fn[a];
+            fn[a] = fq[a];
         }
+        hn = hq;
     }
     if (bad) d.flag[0] = 1;
     if (track) {
@@ -780,9 +812,12 @@ __global__ __launch_bounds__(BLOCK) void fused2_kernel(const InstDev *__restrict
     pl.east_ovf = (unsigned)((cx + 2) % nx) * sizeof(T);
     pl.west_ovf = (unsigned)(tl.x0 == 0 ? nx - 1 : tl.x0 - 1) * sizeof(T);
     const unsigned xlo = (unsigned)(pl.valid ? cx : cx % nx) * sizeof(T);   // pair loaded (wrapped)
-    const bool halo = lane < 2;
-    const int xh = lane == 0 ? (tl.x0 == 0 ? nx - 1 : tl.x0 - 1) : (tl.x0 + SW) % nx;
-    const unsigned xho = (unsigned)xh * sizeof(T);
+    // ring columns: lane 16 c + a (a < 9) loads population a of column c
+    const int hp = lane & 15;
+    const bool hlane = lane < 32 && hp < 9;
+    const int hcol = lane < 16 ? (tl.x0 == 0 ? nx - 1 : tl.x0 - 1) : (tl.x0 + SW) % nx;
+    const unsigned long long hoff = (unsigned long long)(hlane ? hp : 0) * PB + (unsigned)hcol * sizeof(T);
+    const bool hroot = lane == 0 || lane == 16;
     const int hslot = lane == 0 ? 0 : LW - 1;
     const int y_end = min(tl.y0 + H, ny);
     const bool track = walls && (tl.y0 == 0 || tl.y0 + H >= ny);
@@ -791,45 +826,48 @@ __global__ __launch_bounds__(BLOCK) void fused2_kernel(const InstDev *__restrict
 
     bool bad = false;
     double wmax = -INFINITY;
-    V fa[9], fb[9];
+    V fn[9], fa[9], fb[9];
+    T hn = T(0);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
+        fn[a].x = fn[a].y = T(0);
         fa[a].x = fa[a].y = T(0);
         fb[a].x = fb[a].y = T(0);
     }
 
-    // Unrolled by three so that the rotation of the three row buffers
-    // (new -> one ago -> two ago) becomes register renaming, not moves.
-#pragma unroll 3
+    auto row_loaded = [&](int k, int l) { return k < NLOAD && l <= tl.y0 + H && l <= ny; };
+    auto load_row = [&](int k, V v[9], T &h) {
+        const int l = tl.y0 - 1 + ROW_GROUPS * k + w;
+        if (row_loaded(k, l)) {
+            const gptr<const char> rb = f + (unsigned long long)memory_row(l, ny, walls) * RB;
+            if (hlane) h = ld_lane<T>(rb, hoff);
+#pragma unroll
+            for (int a = 0; a < 9; ++a) v[a] = ldp<T>(rb + a * PB, xlo);
+        }
+    };
+    load_row(0, fn, hn);
+
+#pragma unroll 4
     for (int k = 0; k < NK; ++k) {
         const int l = tl.y0 - 1 + ROW_GROUPS * k + w;
-        const bool do_load = k < NLOAD && l <= tl.y0 + H && l <= ny;
-        int mr = l;
-        if (walls) mr = mr < 0 ? 0 : (mr > ny - 1 ? ny - 1 : mr);
-        else mr = mr < 0 ? mr + ny : (mr >= ny ? mr - ny : mr);
-        const gptr<const char> rb = f + (unsigned long long)mr * RB;
-        V fn[9];
+        const bool have = row_loaded(k, l);
+        V fq[9];
+        T hq = T(0);
 #pragma unroll
-        for (int a = 0; a < 9; ++a) fn[a].x = fn[a].y = T(0);
-        T dm_h = T(0);
-        if (do_load && halo) {
-            T fh[9];
-#pragma unroll
-            for (int a = 0; a < 9; ++a) fh[a] = ld<T>(rb + a * PB, xho);
-            dm_h = density<T>(fh);
-        }
-        if (do_load) {
-#pragma unroll
-            for (int a = 0; a < 9; ++a) fn[a] = ldp<T>(rb + a * PB, xlo);
-        }
+        for (int a = 0; a < 9; ++a) fq[a].x = fq[a].y = T(0);
+        load_row(k + 1, fq, hq);
+
         T *row = ring + ((l + 2 * RING) % RING) * LW;
-        if (do_load && halo) {
-            const T ph = pseudopotential<T, EOS64>(dm_h, d);
-            row[hslot] = ph;
-            bad |= !finite_value(ph);
+        if (have) {
+            const T dm_h = halo_density<T>(hn);
+            if (hroot) {
+                const T ph = pseudopotential<T, EOS64>(dm_h, d);
+                row[hslot] = ph;
+                bad |= !finite_value(ph);
+            }
         }
 
-        // collide and push the row loaded two iterations ago
+        // collide and push the row handled two iterations ago
         const int c = l - 2 * ROW_GROUPS;
         if (k >= 2 && c >= tl.y0 && c < y_end) {
             const T *rS = ring + ((c - 1 + 2 * RING) % RING) * LW;
@@ -880,8 +918,8 @@ __global__ __launch_bounds__(BLOCK) void fused2_kernel(const InstDev *__restrict
             }
         }
 
-        // psi of the row loaded now
-        if (do_load) {
+        // psi of the row handled now
+        if (have) {
             T e0[9], e1[9];
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
@@ -904,7 +942,9 @@ __global__ __launch_bounds__(BLOCK) void fused2_kernel(const InstDev *__restrict
         for (int a = 0; a < 9; ++a) {
             fb[a] = fa[a];
             fa[a] = fn[a];
+            fn[a] = fq[a];
         }
+        hn = hq;
     }
     if (bad) d.flag[0] = 1;
     if (track) {
