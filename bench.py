@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="laplace_sweep",
                     choices=["laplace_sweep", "collapse_large", "precision_large", "collapse_horizon",
-                             "laplace_physics"])
+                             "laplace_physics", "coexistence_sweep", "critical_nucleus", "paper_collapse"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-plain", action="store_true")
     ap.add_argument("--variant", type=int, default=-1, help="tile variant; -1 autotunes")
@@ -47,6 +47,15 @@ def parse():
     ap.add_argument("--no-served", action="store_true", help="skip the served-batch latency run")
     ap.add_argument("--tau-nu", type=float, default=0.6, help="tau_nu of the collapse studies")
     ap.add_argument("--delta", type=float, default=0.02, help="liquid over-density of the collapse studies")
+    ap.add_argument("--sigma", type=float, default=0.0111,
+                    help="surface tension for the critical-nucleus study (this model's Laplace fit at 0.5 Tc)")
+    ap.add_argument("--tau-nu-list", type=float, nargs="+", default=[0.51, 0.6],
+                    help="tau_nu values of the paper_collapse study")
+    ap.add_argument("--delta-list", type=float, nargs="+", default=[0.13],
+                    help="liquid over-densities of the paper_collapse study")
+    ap.add_argument("--record-every", type=int, default=0, help="record interval of the paper_collapse study")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp32_mixed"],
+                    help="precision of the paper_collapse study")
     ap.add_argument("--served-requests", type=int, default=512)
     ap.add_argument("--served-budget-gb", type=float, default=8.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -73,17 +82,6 @@ def calibrate_copy(mib):
     assert torch.equal(dst, src)
     print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "ms": ms,
                       "GB_s": 2 * n / (ms * 1e-3) / 1e9}), flush=True)
-
-
-def laplace_sweep_sims(L, precision, device):
-    from paper_1605_01800_amd import inputs
-    sims = []
-    for case in inputs.laplace_sweep_cases(256):
-        p = L.make_params(256, 256, T_over_Tc=case["T_over_Tc"], precision=precision, tau_nu=0.6)
-        s = L.Sim(p, device=device)
-        s.init_bubble(case["bubbles"], slab_rows=case["slab_rows"], W=5.0)
-        sims.append(s)
-    return sims
 
 
 def collapse_large_sims(L, precision, device):
@@ -176,188 +174,6 @@ def served_run(device, n_requests, budget_gb, load=0.8, chunk=500, seed=0):
             "peak_slots": stats["peak_slots"], "nonfinite_requests": bad}
 
 
-# ---- studies: each prints one JSON line of its own -------------------------
-
-def _record(sim):
-    d = sim.diag()
-    return {"step": d["step"], "mass": d["mass"], "radius": d["radius"], "wall_p_max": d["wall_p_max"],
-            "wall_p_step": d["wall_p_step"], "nonfinite": d["nonfinite"]}
-
-
-def _run_history(L, params, init, steps, every, device, variant=None):
-    import torch
-    sim = L.Sim(params, device=device)
-    if variant is not None:
-        sim.set_variant(variant)
-    sim.init_bubble(**init)
-    hist = [_record(sim)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    step_s = 0.0
-    done = 0
-    while done < steps:
-        n = min(every, steps - done)
-        t1 = time.perf_counter()
-        sim.step(n)
-        sim.stream.synchronize()
-        step_s += time.perf_counter() - t1
-        done += n
-        try:
-            hist.append(_record(sim))
-        except L.NonFiniteError:
-            hist.append({"step": done, "nonfinite": True})
-            break
-    total = time.perf_counter() - t0
-    sim.close()
-    return hist, params.nx * params.ny * done / step_s / 1e6, total
-
-
-def _rel_err_history(h, ref, key, k=None):
-    out = []
-    for a, b in zip(h, ref):
-        if a.get("nonfinite") or b.get("nonfinite"):
-            break
-        va = a[key] if k is None else a[key][k]
-        vb = b[key] if k is None else b[key][k]
-        out.append((a["step"], abs(va - vb) / abs(vb) if vb != 0 else abs(va - vb)))
-    return out
-
-
-def precision_study(device, large, steps, every, tau_nu=0.6, delta=0.02):
-    """The same wall-bounded collapse in binary64, binary32 and binary32 with
-    binary64 EOS/psi: MLUPS of each and the relative error of total mass,
-    bubble radii and the wall-pressure peak against binary64."""
-    from paper_1605_01800_amd import inputs
-    from paper_1605_01800_amd import lbm as L
-    if large:
-        nx, ny = 8192, 4096
-        bub = inputs.non_overlapping_discs(nx, ny, [300, 200, 150], W=5.0, seed=0, walls=True)
-        init = dict(bubbles=bub, W=5.0, delta=delta)
-        name = "precision_large"
-    else:
-        nx, ny = 1024, 768
-        bub = [(511.5, 200.0, 120.0)]
-        init = dict(bubbles=bub, W=5.0, delta=delta, noise_amp=1e-3, seed=1)
-        name = "collapse_horizon"
-    runs = {}
-    for prec in ("fp64", "fp32", "fp32_mixed"):
-        p = L.make_params(nx, ny, T_over_Tc=0.6, walls=True, precision=prec, tau_nu=tau_nu)
-        hist, mlups, total = _run_history(L, p, init, steps, every, device,
-                                          variant=L.variant_names().index("fused-64x16"))
-        runs[prec] = {"hist": hist, "mlups": mlups}
-        print("# %s %s: %.0f MLUPS over %d steps (%.1f s)" % (name, prec, mlups, hist[-1]["step"], total),
-              file=sys.stderr, flush=True)
-    ref = runs["fp64"]["hist"]
-    out = {"metric": name, "grid": "%dx%d" % (nx, ny), "walls_y": True, "T_over_Tc": 0.6, "tau_nu": tau_nu,
-           "eps": 1.86, "delta": delta, "bubbles": [list(b) for b in bub], "steps": steps, "record_every": every,
-           "reference": "binary64 GPU path (within 1e-12 of the FP64 oracle over 10^4 steps)", "runs": {}}
-    for prec, r in runs.items():
-        h = r["hist"]
-        e = {"mlups": round(r["mlups"], 1),
-             "bytes_per_site": 144 if prec == "fp64" else 72,
-             "frac_of_8TBs": round(r["mlups"] * 1e6 * (144 if prec == "fp64" else 72) / 8e12, 4),
-             "steps_done": h[-1]["step"], "nonfinite": bool(h[-1].get("nonfinite"))}
-        if prec != "fp64":
-            em = _rel_err_history(h, ref, "mass")
-            e["mass_max_rel_err"] = max(v for _, v in em)
-            er = [_rel_err_history(h, ref, "radius", k) for k in range(len(bub))]
-            e["radius_max_rel_err"] = [max(v for _, v in x) for x in er]
-            e["radius_rel_err_vs_step"] = [[s_, max(x[i][1] for x in er)] for i, (s_, _) in enumerate(er[0])]
-            hl, rl = h[-1], ref[min(len(ref), len(h)) - 1]
-            if not hl.get("nonfinite") and not rl.get("nonfinite"):
-                e["wall_p_max"] = hl["wall_p_max"]
-                e["wall_p_max_rel_err"] = abs(hl["wall_p_max"] - rl["wall_p_max"]) / abs(rl["wall_p_max"])
-                e["wall_p_step"] = hl["wall_p_step"]
-                e["wall_p_step_ref"] = rl["wall_p_step"]
-        else:
-            e["radius_history"] = [[x["step"]] + list(x["radius"]) for x in h if not x.get("nonfinite")]
-            e["wall_p_max"] = h[-1].get("wall_p_max")
-            e["wall_p_step"] = h[-1].get("wall_p_step")
-        out["runs"][prec] = e
-    print(json.dumps(out), flush=True)
-
-
-def laplace_physics(device, steps):
-    """The sweep run to equilibrium in binary32: per temperature the surface
-    tension from a least-squares line of the pressure jump against 1/R (Eq. 17,
-    reported as p_in - p_out), and the slab's coexisting densities against the
-    Maxwell rule (Eq. 11)."""
-    import numpy as np
-    from paper_1605_01800_amd import lbm as L
-    from paper_1605_01800_amd import inputs
-    sims = laplace_sweep_sims(L, "fp32", device)
-    cases = inputs.laplace_sweep_cases(256)
-    batch = L.Batch(precision="fp32", max_instances=len(sims), max_tiles=sum(L.tile_count(s.params) for s in sims),
-                    device=device)
-    for s in sims:
-        batch.attach(s)
-    batch.set_variant(L.variant_names().index("fused-64x16"))
-    # The acoustic transient of the initial profile decays slowly at tau_nu
-    # = 0.6 (the slowest mode of a 256 box has a decay time of ~2e4 steps), so
-    # the pressure jump and the slab densities are averaged over samples
-    # every 250 steps in the last quarter of the run.
-    n = 256
-    yy, xx = np.mgrid[0:n, 0:n]
-    c = 0.5 * (n - 1)
-    r = np.hypot(xx - c, yy - c)
-    t0 = time.perf_counter()
-    batch.step(steps - steps // 4)
-    batch.sync()
-    dt = time.perf_counter() - t0
-    sample_every = 250
-    nsamp = max(1, (steps // 4) // sample_every)
-    acc = [dict(dp=0.0, R=0.0, rl=0.0, rg=0.0) for _ in sims]
-    for k in range(nsamp):
-        t1 = time.perf_counter()
-        batch.step(sample_every)
-        batch.sync()
-        dt += time.perf_counter() - t1
-        for a, s, case in zip(acc, sims, cases):
-            m = s.macros()
-            rho = m["rho"].double().cpu().numpy()
-            if case["slab_rows"]:
-                prof = rho.mean(axis=1)
-                lm, gm = int(round(c)), int(round(c + n / 2)) % n
-                a["rl"] += float(np.mean(prof[[(lm + j) % n for j in range(-8, 9)]])) / nsamp
-                a["rg"] += float(np.mean(prof[[(gm + j) % n for j in range(-8, 9)]])) / nsamp
-            else:
-                p = m["p"].cpu().numpy()
-                R = m["diag"]["radius"][0]
-                a["R"] += R / nsamp
-                a["dp"] += float(p[r < R - 10.0].mean() - p[r > R + 10.0].mean()) / nsamp
-    per_T = {}
-    for a, case in zip(acc, cases):
-        tr = case["T_over_Tc"]
-        g, l, _ = L.maxwell(L.temperature(tr))
-        e = per_T.setdefault(tr, {"R": [], "dp": [], "maxwell": (g, l)})
-        if case["slab_rows"]:
-            e["slab_rho_l"], e["slab_rho_g"] = a["rl"], a["rg"]
-        else:
-            e["R"].append(a["R"])
-            e["dp"].append(a["dp"])
-    out = {"metric": "laplace_physics", "grid": "256x256", "steps": steps, "tau_nu": 0.6, "eps": 1.86,
-           "averaged_over": "%d samples every %d steps in the last quarter" % (nsamp, sample_every),
-           "precision": "fp32", "seconds": round(dt, 2), "mlups": round(len(sims) * n * n * steps / dt / 1e6, 1),
-           "temperatures": {}}
-    for tr, e in sorted(per_T.items()):
-        x = 1.0 / np.array(e["R"])
-        y = np.array(e["dp"])
-        A = np.vstack([x, np.ones_like(x)]).T
-        (sig, c0), *_ = np.linalg.lstsq(A, y, rcond=None)
-        yf = sig * x + c0
-        r2 = 1 - np.sum((y - yf) ** 2) / np.sum((y - y.mean()) ** 2)
-        g, l = e["maxwell"]
-        out["temperatures"][str(tr)] = {
-            "radii": [round(v, 3) for v in e["R"]], "dp": e["dp"], "sigma": float(sig), "intercept": float(c0),
-            "r2": float(r2), "slab_rho_l": e.get("slab_rho_l"), "slab_rho_g": e.get("slab_rho_g"),
-            "maxwell_rho_l": l, "maxwell_rho_g": g,
-            "rho_l_rel_dev": (e["slab_rho_l"] - l) / l, "rho_g_rel_dev": (e["slab_rho_g"] - g) / g}
-    batch.close()
-    for s in sims:
-        s.close()
-    print(json.dumps(out), flush=True)
-
-
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -372,21 +188,32 @@ def main():
 
     device = "cuda:0"
     torch.cuda.set_device(0)
+    from paper_1605_01800_amd import studies
     if args.workload == "precision_large":
-        precision_study(device, True, steps=args.steps, every=max(1, args.steps // 20), tau_nu=args.tau_nu,
-                        delta=args.delta)
+        studies.precision_study(device, True, steps=args.steps, every=max(1, args.steps // 20),
+                                tau_nu=args.tau_nu, delta=args.delta)
         return
     if args.workload == "collapse_horizon":
-        precision_study(device, False, steps=args.steps, every=max(1, args.steps // 100), tau_nu=args.tau_nu,
-                        delta=args.delta)
+        studies.precision_study(device, False, steps=args.steps, every=max(1, args.steps // 100),
+                                tau_nu=args.tau_nu, delta=args.delta)
         return
     if args.workload == "laplace_physics":
-        laplace_physics(device, steps=args.steps)
+        studies.laplace_physics(device, steps=args.steps)
+        return
+    if args.workload == "coexistence_sweep":
+        studies.coexistence_sweep(device, steps=args.steps)
+        return
+    if args.workload == "critical_nucleus":
+        studies.critical_nucleus(device, steps=args.steps, sigma=args.sigma)
+        return
+    if args.workload == "paper_collapse":
+        studies.paper_collapse(device, steps=args.steps, every=args.record_every or max(1, args.steps // 200),
+                               tau_nu=args.tau_nu_list, delta=args.delta_list, precision=args.precision)
         return
     precision = "fp32"
     es = 4
     if args.workload == "laplace_sweep":
-        sims = laplace_sweep_sims(L, precision, device)
+        sims = studies.laplace_sweep_sims(L, precision, device)
         workload = {"workload": "laplace_sweep", "instances": len(sims), "grid": "256x256",
                     "periodic": True, "T_over_Tc": [0.6, 0.7, 0.8, 0.9], "radii": [20, 30, 40, 50, 60],
                     "slab_rows": 128, "tau_nu": 0.6, "eps": 1.86}
