@@ -3,16 +3,21 @@ MI355X.
 
 Default workload: the Laplace-law and coexistence sweep (24 instances of a
 256 x 256 periodic grid: discs of radius 20..60 at T/Tc 0.6..0.9 plus one liquid
-slab per temperature), binary32, stepped as one batch: each step is one launch
-of the psi pass and one launch of the force+collide+stream pass over the tiles
-of all 24 instances, replayed from captured HIP graphs.  A "step" advances all
-24 instances by one timestep.
+slab per temperature), binary32, stepped as one batch over the tiles of all 24
+instances with the tile variant the autotuner picks (normally the fused
+single-pass kernel: one launch per step), replayed from captured HIP graphs.  A
+"step" advances all 24 instances by one timestep.
 
 Prints one JSON line: aggregate MLUPS (million lattice-site updates per second),
-the roofline of the dominant kernel (HBM bytes of the stated per-site model over
-its event-timed duration), the oracle's CPU rate on a bounded sample, and the
-plain per-instance binary64 rate (one instance at a time, one launch pair per
-step, no graph, no batch) that the batched binary32 rate is compared with.
+the roofline of the dominant kernel (algorithmic HBM bytes of the stated
+per-site model over its timed duration, and the measured HBM traffic when a
+counter record for the current kernel source exists), the oracle's CPU rate on
+a bounded sample, the plain per-instance binary64 rate (one instance at a time,
+direct launches, no graph, no batch) and the served-batch latencies.
+
+Other workloads: collapse_large (one 8192 x 4096 wall-bounded grid, HBM
+resident) and the experiment drivers of paper_1605_01800_amd.studies, each
+printing its own JSON line.
 """
 import argparse
 import json
@@ -30,6 +35,28 @@ BYTES_PSI = {4: 9 * 4 + 4, 8: 9 * 8 + 8}
 BYTES_COLLIDE = {4: 9 * 4 + 4 + 9 * 4, 8: 9 * 8 + 8 + 9 * 8}
 # the fused kernel reads the nine populations and writes nine (psi stays in LDS)
 BYTES_FUSED = {4: 18 * 4, 8: 18 * 8}
+
+
+def measured_traffic(workload, variant_name):
+    """HBM bytes per launch of the dominant kernel from the rocprofv3 FETCH_SIZE
+    and WRITE_SIZE counters recorded in profiles/traffic.json (each scaled by
+    what the counter reads for a copy kernel of known size), or None when no
+    record matches this workload and tile variant or the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_1605_01800_amd", "csrc", "lbm_kernels.hip")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+        with open(src, "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    e = rec.get("entries", {}).get(workload)
+    if rec.get("kernels_source_sha256") != sha or not e or e.get("variant") != variant_name:
+        return None
+    return e["bytes_per_launch"]
 
 
 def parse():
@@ -281,6 +308,7 @@ def main():
     print("# dominant %s %.4f ms/launch, %.0f GB/s of %d B/site" % (dominant[0], dominant[1], achieved,
                                                                      dominant[2]), file=sys.stderr, flush=True)
 
+    traffic = measured_traffic(args.workload, vname)
     out = {
         "metric": "aggregate MLUPS + %HBM roofline (FP32 batched vs FP64 plain); p50/p99 latency",
         "value": round(mlups, 1),
@@ -302,9 +330,11 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
             "bytes_per_site": dominant[2],
             "launch_ms": dominant[1],
+            "algorithmic_bytes_per_launch": dominant[2] * sites,
+            "traffic_over_algorithmic": None if traffic is None else round(traffic / (dominant[2] * sites), 4),
         },
         "kernels": kernels,
     }
