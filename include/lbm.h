@@ -214,8 +214,8 @@ const char *lbm_variant_name(int variant);
 int lbm_set_variant(void *handle, int variant);
 int lbm_batch_set_variant(void *batch, int variant);
 /* Times every variant on the batch's current instances with HIP events, in
- * three rounds of min(reps, 8) warm-up steps and reps timed steps each, scores
- * each variant by its fastest round, selects the best and returns it with its
+ * three passes of min(reps, 8) warm-up steps and reps timed steps each, scores
+ * each variant by its fastest pass, selects the best and returns it with its
  * time per step.  It advances the instances' state (call it on throwaway
  * state or before initialising). */
 int lbm_batch_autotune(void *batch, int reps, int *best_variant, float *ms_per_step);

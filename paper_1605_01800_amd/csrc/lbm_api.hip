@@ -985,13 +985,13 @@ int lbm_batch_autotune(void *batch, int reps, int *best_variant, float *ms_per_s
     hipEvent_t e0, e1;
     TRYHIP(hipEventCreate(&e0));
     TRYHIP(hipEventCreate(&e1));
-    // Three rounds over the variants, each variant scored by its fastest
-    // round, so that a single disturbed measurement does not decide.
-    constexpr int kRounds = 3;
+    // Three passes over the variants, each variant scored by its fastest
+    // pass, so that a single disturbed measurement does not decide.
+    constexpr int kPasses = 3;
     float score[kNumVariants];
     for (int v = 0; v < kNumVariants; ++v) score[v] = INFINITY;
     int rc = LBM_OK;
-    for (int round = 0; round < kRounds && rc == LBM_OK; ++round) {
+    for (int pass = 0; pass < kPasses && rc == LBM_OK; ++pass) {
         for (int v = 0; v < kNumVariants && rc == LBM_OK; ++v) {
             bool fits = true;
             for (Instance *h : b->members) fits = fits && variant_fits(v, h->p.nx);
