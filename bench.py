@@ -66,7 +66,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="laplace_sweep",
                     choices=["laplace_sweep", "collapse_large", "precision_large", "collapse_horizon",
-                             "laplace_physics", "coexistence_sweep", "critical_nucleus", "paper_collapse"])
+                             "laplace_physics", "coexistence_sweep", "critical_nucleus", "paper_collapse",
+                             "single_small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-plain", action="store_true")
     ap.add_argument("--variant", type=int, default=-1, help="tile variant; -1 autotunes")
@@ -119,6 +120,37 @@ def collapse_large_sims(L, precision, device):
     s = L.Sim(p, device=device)
     s.init_bubble(bub, W=5.0, delta=0.02)
     return [s]
+
+
+def single_small(device, steps, warmup):
+    """One 64 x 64 periodic instance in binary64 (T = 0.7 T_c, a disc of
+    radius 16 at the centre, W = 2, tau_nu = 0.8, the 64^2 check of
+    Section 3.1): a launch-bound case (0.3 MB of populations), stepped through
+    captured graphs of 256 steps on the instance's own stream, for each tile
+    variant."""
+    import torch
+    from paper_1605_01800_amd import lbm as L
+    p = L.make_params(64, 64, T_over_Tc=0.7, precision="fp64", tau_nu=0.8)
+    out = {"metric": "single_instance_mlups", "grid": "64x64", "precision": "fp64", "steps": steps,
+           "variants": {}}
+    for v, name in enumerate(L.variant_names()):
+        s = L.Sim(p, device=device)
+        s.set_variant(v)
+        s.init_bubble([(31.5, 31.5, 16.0)], W=2.0)
+        s.step(warmup)
+        s.sync()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        s.step(steps)
+        e1.record(s.stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        out["variants"][name] = {"mlups": round(64 * 64 * steps / (ms * 1e-3) / 1e6, 1),
+                                 "us_per_step": round(ms * 1e3 / steps, 3)}
+        s.close()
+    best = max(out["variants"].items(), key=lambda kv: kv[1]["mlups"])
+    out["best"] = {"variant": best[0], **best[1]}
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(seconds):
@@ -226,6 +258,9 @@ def main():
         return
     if args.workload == "laplace_physics":
         studies.laplace_physics(device, steps=args.steps)
+        return
+    if args.workload == "single_small":
+        single_small(device, steps=args.steps, warmup=args.warmup)
         return
     if args.workload == "coexistence_sweep":
         studies.coexistence_sweep(device, steps=args.steps)

@@ -228,6 +228,13 @@ class Sim:
                                 self.stream.cuda_stream, ctypes.byref(h)), "lbm_create")
         self.h = h
         self.rho_l = self.rho_g = None
+        self._batch = None
+
+    @property
+    def work_stream(self):
+        """The stream the library enqueues this instance's work on: its own, or
+        the batch's while it is attached to one."""
+        return self._batch.stream if self._batch is not None else self.stream
 
     # -- state --------------------------------------------------------------
     def init_bubble(self, bubbles=(), slab_rows=0, rho_l=None, rho_g=None, W=5.0, delta=0.0,
@@ -249,11 +256,12 @@ class Sim:
             rho_l = l if rho_l is None else rho_l
             rho_g = g if rho_g is None else rho_g
         self.rho_l, self.rho_g = rho_l, rho_g
-        with torch.cuda.stream(self.stream):
+        ws = self.work_stream
+        with torch.cuda.stream(ws):
             r = torch.as_tensor(rho, dtype=torch.float64).to(self.device).contiguous()
         assert r.shape == (self.ny, self.nx)
         _check(lib().lbm_init_density(self.h, r.data_ptr(), rho_l, rho_g), "lbm_init_density")
-        self.stream.synchronize()
+        ws.synchronize()
         return self
 
     def step(self, n=1):
@@ -279,7 +287,7 @@ class Sim:
         out = {}
         ptrs = [None] * 4
         if fields:
-            with torch.cuda.stream(self.stream):
+            with torch.cuda.stream(self.work_stream):
                 for k, dt in zip(("rho", "ux", "uy", "p"), (self.dtype,) * 3 + (torch.float64,)):
                     out[k] = torch.empty((self.ny, self.nx), dtype=dt, device=self.device)
             ptrs = [out[k].data_ptr() for k in ("rho", "ux", "uy", "p")]
@@ -293,18 +301,20 @@ class Sim:
 
     def populations(self):
         """Post-streaming populations, tensor (9, ny, nx)."""
-        with torch.cuda.stream(self.stream):
+        ws = self.work_stream
+        with torch.cuda.stream(ws):
             f = torch.empty((9, self.ny, self.nx), dtype=self.dtype, device=self.device)
         _check(lib().lbm_get_populations(self.h, f.data_ptr()), "lbm_get_populations")
-        self.stream.synchronize()
+        ws.synchronize()
         return f
 
     def set_populations(self, f):
         f = f.to(device=self.device, dtype=self.dtype).contiguous()
         assert f.shape == (9, self.ny, self.nx)
-        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        ws = self.work_stream
+        ws.wait_stream(torch.cuda.current_stream(self.device))
         _check(lib().lbm_set_populations(self.h, f.data_ptr()), "lbm_set_populations")
-        self.stream.synchronize()
+        ws.synchronize()
         return self
 
     def save(self):
@@ -354,10 +364,12 @@ class Batch:
     def attach(self, sim):
         _check(lib().lbm_batch_attach(self.b, sim.h), "lbm_batch_attach")
         self.members.append(sim)
+        sim._batch = self
 
     def detach(self, sim):
         _check(lib().lbm_batch_detach(self.b, sim.h), "lbm_batch_detach")
         self.members.remove(sim)
+        sim._batch = None
 
     def step(self, n=1):
         _check(lib().lbm_batch_step(self.b, int(n)), "lbm_batch_step")
@@ -388,6 +400,8 @@ class Batch:
         if getattr(self, "b", None) is not None and self.b.value:
             lib().lbm_batch_destroy(self.b)
             self.b = ctypes.c_void_p()
+            for m in self.members:
+                m._batch = None
             self.members = []
 
     def __del__(self):

@@ -1,0 +1,108 @@
+"""Parity at the workloads' full sizes, in the launch configuration bench.py
+times (one batch over all instances, the tile variant its autotuner picks):
+
+  * the Laplace-law sweep, 24 instances of 256 x 256: after 300 steps every
+    site of every instance is compared with one oracle step from the same state;
+  * the 8192 x 4096 wall-bounded three-disc collapse: after 200 steps, windows
+    at the walls, across the periodic x edge, across strip edges and on a disc
+    interface are compared with one oracle step of the window.  A window's
+    outer three rows and columns are left out where the window is not bounded
+    by a wall (one step reaches two sites: psi of a neighbour, then streaming),
+    so the compared sites see exactly the state the GPU saw.
+
+Tolerances as for single steps: 1e-14 relative (binary64), 2e-6 (binary32).
+"""
+import numpy as np
+import pytest
+
+from oracle import stepper as ostep
+from tests.helpers import oracle_params, rel_inf, to_oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+L = pytest.importorskip("paper_1605_01800_amd.lbm")
+from paper_1605_01800_amd import inputs, studies  # noqa: E402
+
+STEP_TOL = {"fp64": 1e-14, "fp32": 2e-6}
+
+
+def _batch(sims, precision, variant):
+    b = L.Batch(precision=precision, max_instances=len(sims),
+                max_tiles=sum(L.tile_count(s.params) for s in sims))
+    for s in sims:
+        b.attach(s)
+    b.set_variant(L.variant_names().index(variant))
+    return b
+
+
+@pytest.mark.parametrize("variant", ["fused-64x16", "fused2-128x16"])
+def test_laplace_sweep_full_size_one_step(variant):
+    print("case sweep", variant, flush=True)
+    sims = studies.laplace_sweep_sims(L, "fp32", "cuda:0")
+    b = _batch(sims, "fp32", variant)
+    b.step(300)
+    b.sync()
+    starts = [s.populations() for s in sims]
+    b.step(1)
+    b.sync()
+    for s, f0 in zip(sims, starts):
+        want = to_oracle(f0)
+        assert ostep.step(oracle_params(s.params), want, 1) == 0
+        got = to_oracle(s.populations())
+        assert rel_inf(got, want) < STEP_TOL["fp32"]
+    b.close()
+    for s in sims:
+        s.close()
+
+
+def _windows(nx, ny, bub, h=32, w=40):
+    """(rows, columns, bottom wall, top wall) of the sample windows."""
+    x0, y0, r0 = bub[0]
+    xi, yi = int(x0 + r0) - w // 2, int(y0) - h // 2           # across the first disc's interface
+    out = [
+        (np.arange(0, h), np.arange(1000, 1000 + w), True, False),                 # bottom wall
+        (np.arange(ny - h, ny), np.arange(5000, 5000 + w), False, True),           # top wall
+        (np.arange(ny // 2, ny // 2 + h), np.r_[nx - w // 2:nx, 0:w // 2], False, False),  # x edge
+        (np.arange(0, h), np.r_[nx - w // 2:nx, 0:w // 2], True, False),           # corner
+        (np.arange(1717, 1717 + h), np.arange(128 * 20 - w // 2, 128 * 20 + w // 2), False, False),  # strips
+        (np.arange(yi, yi + h), np.arange(xi, xi + w), False, False),              # interface
+    ]
+    return out
+
+
+@pytest.mark.parametrize("prec,variant", [("fp32", "fused2-128x16"), ("fp32", "fused-64x16"),
+                                          ("fp64", "fused-64x16")])
+def test_collapse_large_full_size_sampled_windows(prec, variant):
+    print("case large", prec, variant, flush=True)
+    nx, ny = 8192, 4096
+    bub = inputs.non_overlapping_discs(nx, ny, [300, 200, 150], W=5.0, seed=0, walls=True)
+    p = L.make_params(nx, ny, T_over_Tc=0.6, walls=True, precision=prec, tau_nu=0.51)
+    sim = L.Sim(p)
+    sim.init_bubble(bub, W=5.0, delta=0.02)
+    b = _batch([sim], prec, variant)
+    b.step(200)
+    b.sync()
+    f0 = sim.populations()
+    b.step(1)
+    b.sync()
+    f1 = sim.populations()
+    P = oracle_params(p)
+    for rows, cols, bottom, top in _windows(nx, ny, bub):
+        r = torch.as_tensor(rows, device=f0.device)
+        c = torch.as_tensor(cols, device=f0.device)
+        sub0 = f0.index_select(1, r).index_select(2, c)
+        sub1 = f1.index_select(1, r).index_select(2, c)
+        h, w = len(rows), len(cols)
+        Pw = ostep.with_grid(P, w, h, walls=bottom or top)
+        want = to_oracle(sub0)
+        assert ostep.step(Pw, want, 1) == 0
+        got = to_oracle(sub1)
+        ylo = 0 if bottom else 3
+        yhi = h if top else h - 3
+        sl = (slice(ylo, yhi), slice(3, w - 3))
+        err = rel_inf(got[sl], want[sl])
+        print("window rows %d.. cols %d.. err %.2e" % (rows[0], cols[0], err), flush=True)
+        assert err < STEP_TOL[prec]
+    b.close()
+    sim.close()

@@ -287,3 +287,31 @@ def test_wall_pressure_peak_matches_oracle(variant):
     assert d["wall_p_step"] == best_step
     assert abs(d["wall_p_max"] - best) <= 1e-12 * abs(best)
     sim.close()
+
+
+def test_attached_instance_reads_follow_batch_work():
+    """Reads of an instance attached to a batch run on the batch's stream, so
+    a read right after batch steps (no explicit sync) sees those steps: the
+    populations equal the ones read after a sync and a detach, and the
+    diagnostics count the steps."""
+    print("case attached reads", flush=True)
+    p = L.make_params(2048, 1024, T_over_Tc=0.7, walls=True, precision="fp32", tau_nu=0.6)
+    sim = L.Sim(p).init_bubble([(1023.5, 400.0, 150.0)], W=5.0, delta=0.02)
+    b = L.Batch(precision="fp32", max_instances=1, max_tiles=L.tile_count(p))
+    b.attach(sim)
+    b.set_variant(_variant("fused2-128x16"))
+    for k in range(3):
+        b.step(40)
+        early = sim.populations()
+        b.sync()
+        assert sim.diag()["step"] == 40 * (k + 1)
+        assert torch.equal(early, sim.populations())
+    b.step(40)
+    rho = sim.macros()["rho"]
+    b.detach(sim)
+    late = sim.populations()
+    assert torch.equal(rho, sim.macros()["rho"])
+    assert sim.diag()["step"] == 160
+    assert late.shape == (9, 1024, 2048)
+    b.close()
+    sim.close()
