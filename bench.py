@@ -321,12 +321,12 @@ def main():
     # steps).  Two-pass variants time each launch with its own event pair on the
     # batch's stream.
     vname = L.variant_names()[variant]
-    fused = vname.startswith("fused")
+    fused = not vname.startswith("2pass")
     nk = min(args.steps, 100)
     ms_psi, ms_col = batch.step_timed(nk)
     if fused:
         t_dom = ms / args.steps
-        kname = "fused2_kernel" if vname.startswith("fused2") else "fused_kernel"
+        kname = {"fused2": "fused2_kernel", "fused": "fused_kernel"}[vname.split("-")[0]]
         dominant = (kname, t_dom, BYTES_FUSED[es])
         kernels = {kname: {"ms_region_avg": t_dom, "ms_event_pair_avg": ms_col / nk,
                                     "bytes_per_site": BYTES_FUSED[es],
