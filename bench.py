@@ -71,7 +71,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-plain", action="store_true")
     ap.add_argument("--variant", type=int, default=-1, help="tile variant; -1 autotunes")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-served", action="store_true", help="skip the served-batch latency run")
     ap.add_argument("--tau-nu", type=float, default=0.6, help="tau_nu of the collapse studies")
     ap.add_argument("--delta", type=float, default=0.02, help="liquid over-density of the collapse studies")
@@ -153,28 +153,50 @@ def single_small(device, steps, warmup):
     print(json.dumps(out), flush=True)
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(seconds):
     """The FP64 oracle on one 256 x 256 instance of the sweep (R = 40 at
-    0.7 T_c), steps sized to take about `seconds`."""
+    0.7 T_c), steps sized to take about `seconds` on all the threads its
+    OpenMP runtime uses, then a shorter sample on one thread."""
     from oracle import coexist, stepper
     from oracle import build as obuild
     obuild.ensure_built()
     T = coexist.temperature(0.7)
     rg, rl, _ = coexist.maxwell(T)
     P = stepper.make_params(256, 256, T, tau_nu=0.6)
-    f = stepper.init_populations(P, stepper.init_density(P, bubbles=[(127.5, 127.5, 40.0)],
-                                                         rho_l=rl, rho_g=rg, W=5.0))
-    t0 = time.perf_counter()
-    stepper.step(P, f, 3)
-    per = (time.perf_counter() - t0) / 3
-    n = max(3, int(seconds / per))
-    t0 = time.perf_counter()
-    rc = stepper.step(P, f, n)
-    dt = time.perf_counter() - t0
-    assert rc == 0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+    def timed(secs):
+        f = stepper.init_populations(P, stepper.init_density(P, bubbles=[(127.5, 127.5, 40.0)],
+                                                             rho_l=rl, rho_g=rg, W=5.0))
+        t0 = time.perf_counter()
+        stepper.step(P, f, 3)
+        per = (time.perf_counter() - t0) / 3
+        n = max(3, int(secs / per))
+        t0 = time.perf_counter()
+        rc = stepper.step(P, f, n)
+        dt = time.perf_counter() - t0
+        assert rc == 0
+        return n, dt
+
+    threads = stepper.threads()
+    n, dt = timed(seconds)
+    stepper.set_threads(1)
+    n1, dt1 = timed(seconds / 5)
+    stepper.set_threads(threads)
     return {"value": 256 * 256 * n / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": "1 of the 24 sweep instances (256x256, R=40, 0.7 Tc), %d steps, %.1f s" % (n, dt)}
+            "sample": "1 of the 24 sweep instances (256x256, R=40, 0.7 Tc), %d steps, %.1f s" % (n, dt),
+            "single_thread_value": 256 * 256 * n1 / dt1 / 1e6,
+            "single_thread_sample": "%d steps, %.1f s" % (n1, dt1), "cpu_model": _cpu_model()}
 
 
 def fp64_plain(L, device, steps):

@@ -163,6 +163,10 @@ int lbm_load(void *handle, const void *host_buf, size_t bytes);
 
 /* Synchronises the stream and reports LBM_ENONFINITE if the latch is set. */
 int lbm_sync(void *handle);
+/* Non-blocking completion query: *done = 1 when all work enqueued for the
+ * handle (on the batch's stream while it is attached) has finished, 0 while
+ * some is pending.  Does not read the non-finite latch (lbm_sync does). */
+int lbm_poll(void *handle, int *done);
 
 /* Releases the handle's host metadata and graphs (not the caller's memory). */
 void lbm_destroy(void *handle);
@@ -198,6 +202,8 @@ int lbm_batch_step(void *batch, int64_t n);
  * unchanged afterwards.  Asynchronous. */
 int lbm_batch_step_each(void *batch, const int64_t *counts, int n_counts);
 int lbm_batch_size(void *batch, int *n_attached);
+/* Non-blocking completion query of the batch's stream, as lbm_poll. */
+int lbm_batch_poll(void *batch, int *done);
 void lbm_batch_destroy(void *batch);
 
 /* ---- kernel variants and measurement -------------------------------------- */

@@ -31,6 +31,9 @@
  */
 #include <math.h>
 #include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -447,4 +450,24 @@ void oracle_velocities(int *e_out)
         e_out[2 * a] = EX[a];
         e_out[2 * a + 1] = EY[a];
     }
+}
+
+/* Threads the OpenMP loops use, and a way to change it (for timing the oracle
+ * on one core and on all of them). */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }

@@ -51,6 +51,8 @@ def lib():
         L.oracle_init_populations.argtypes = [P, dp, dp]
         L.oracle_transform.argtypes = [dp, dp]
         L.oracle_velocities.argtypes = [ctypes.POINTER(ctypes.c_int)]
+        L.oracle_threads.restype = ctypes.c_int
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -207,3 +209,12 @@ def velocities():
     e = (ctypes.c_int * 18)()
     lib().oracle_velocities(e)
     return np.array(list(e)).reshape(9, 2)
+
+
+def threads():
+    """Threads the oracle's OpenMP loops use."""
+    return lib().oracle_threads()
+
+
+def set_threads(n):
+    lib().oracle_set_threads(int(n))

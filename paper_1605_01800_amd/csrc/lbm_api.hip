@@ -674,6 +674,28 @@ int lbm_sync(void *handle)
     return read_latch(h);
 }
 
+static int query_stream(hipStream_t st, int *done)
+{
+    const hipError_t e = hipStreamQuery(st);
+    if (e == hipSuccess) {
+        *done = 1;
+        return LBM_OK;
+    }
+    if (e == hipErrorNotReady) {
+        (void)hipGetLastError();   // not an error: clear it
+        *done = 0;
+        return LBM_OK;
+    }
+    return LBM_EHIP;
+}
+
+int lbm_poll(void *handle, int *done)
+{
+    Instance *h = (Instance *)handle;
+    if (!h || !done) return LBM_EINVAL;
+    return query_stream(stream_of(h), done);
+}
+
 int lbm_macros(void *handle, void *d_rho, void *d_ux, void *d_uy, void *d_p, lbm_diag *out)
 {
     Instance *h = (Instance *)handle;
@@ -938,6 +960,13 @@ int lbm_batch_size(void *batch, int *n_attached)
     if (!b || !n_attached) return LBM_EINVAL;
     *n_attached = (int)b->members.size();
     return LBM_OK;
+}
+
+int lbm_batch_poll(void *batch, int *done)
+{
+    Batch *b = (Batch *)batch;
+    if (!b || !done) return LBM_EINVAL;
+    return query_stream(b->stream, done);
 }
 
 int lbm_batch_step(void *batch, int64_t n)

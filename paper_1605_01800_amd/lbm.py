@@ -87,6 +87,7 @@ _SIGS = {
     "lbm_save": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t],
     "lbm_load": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t],
     "lbm_sync": [ctypes.c_void_p],
+    "lbm_poll": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)],
     "lbm_destroy": [ctypes.c_void_p],
     "lbm_strerror": [ctypes.c_int],
     "lbm_batch_workspace_bytes": [ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)],
@@ -98,6 +99,7 @@ _SIGS = {
     "lbm_batch_step_each": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int],
     "lbm_batch_step_timed": [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_float)],
     "lbm_batch_size": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)],
+    "lbm_batch_poll": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)],
     "lbm_batch_destroy": [ctypes.c_void_p],
     "lbm_batch_set_variant": [ctypes.c_void_p, ctypes.c_int],
     "lbm_batch_autotune": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
@@ -281,6 +283,12 @@ class Sim:
     def sync(self):
         _check(lib().lbm_sync(self.h), "lbm_sync")
 
+    def poll(self):
+        """True when all work enqueued for this instance has finished."""
+        done = ctypes.c_int()
+        _check(lib().lbm_poll(self.h, ctypes.byref(done)), "lbm_poll")
+        return bool(done.value)
+
     def macros(self, fields=True):
         """dict with rho, ux, uy (population precision), p (float64) tensors of
         shape (ny, nx) when fields is true, and the diagnostics."""
@@ -395,6 +403,12 @@ class Batch:
 
     def sync(self):
         self.stream.synchronize()
+
+    def poll(self):
+        """True when all work enqueued on the batch's stream has finished."""
+        done = ctypes.c_int()
+        _check(lib().lbm_batch_poll(self.b, ctypes.byref(done)), "lbm_batch_poll")
+        return bool(done.value)
 
     def close(self):
         if getattr(self, "b", None) is not None and self.b.value:

@@ -315,3 +315,24 @@ def test_attached_instance_reads_follow_batch_work():
     assert late.shape == (9, 1024, 2048)
     b.close()
     sim.close()
+
+
+def test_poll_reports_completion():
+    """lbm_poll / lbm_batch_poll never block and report done once the work
+    has finished."""
+    print("case poll", flush=True)
+    p = L.make_params(1024, 1024, T_over_Tc=0.7, precision="fp32", tau_nu=0.6)
+    sim = L.Sim(p).init_bubble([(511.5, 511.5, 100.0)], W=5.0)
+    sim.step(500)
+    assert isinstance(sim.poll(), bool)
+    sim.sync()
+    assert sim.poll()
+    b = L.Batch(precision="fp32", max_instances=1, max_tiles=L.tile_count(p))
+    b.attach(sim)
+    b.step(500)
+    assert isinstance(b.poll(), bool) and isinstance(sim.poll(), bool)
+    b.sync()
+    assert b.poll() and sim.poll()
+    assert sim.diag()["step"] == 1000
+    b.close()
+    sim.close()
