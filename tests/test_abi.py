@@ -80,3 +80,17 @@ def test_workspace_grows_with_precision_and_grid():
     c = L.workspace_bytes(L.make_params(512, 256, T_over_Tc=0.7, precision="fp32"))
     assert 2 * 9 * 256 * 256 * 4 < a < b and a < c
     assert L.tile_count(L.make_params(100, 37, T_over_Tc=0.7)) == 2 * 10
+
+
+def test_largest_accepted_plane():
+    """A population plane (plus its 256-byte skew) must stay below 4 GiB: the
+    largest binary32 grid of width 32768 has 32767 rows, binary64 16383."""
+    L = pytest.importorskip("paper_1605_01800_amd.lbm")
+    lib = L.lib()
+    n = ctypes.c_size_t()
+    for prec, rows in (("fp32", 32767), ("fp64", 16383)):
+        ok = L.make_params(32768, rows, T_over_Tc=0.7, precision=prec)
+        assert lib.lbm_workspace_bytes(ctypes.byref(ok), ctypes.byref(n)) == 0, prec
+        assert n.value > 19 * 32768 * rows * (4 if prec == "fp32" else 8)
+        over = L.make_params(32768, rows + 1, T_over_Tc=0.7, precision=prec)
+        assert lib.lbm_workspace_bytes(ctypes.byref(over), ctypes.byref(n)) == -1, prec

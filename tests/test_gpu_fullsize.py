@@ -106,3 +106,51 @@ def test_collapse_large_full_size_sampled_windows(prec, variant):
         assert err < STEP_TOL[prec]
     b.close()
     sim.close()
+
+
+def test_largest_plane_sampled_windows():
+    """The largest accepted binary32 grid, 32768 x 32767 with walls: every
+    population plane just under 4 GiB (76 GB of workspace).  From an Eq. 16
+    state, one step of each single-pass kernel family is compared with the
+    oracle on windows at the far ends of the planes (the largest offsets)."""
+    free, _ = torch.cuda.mem_get_info()
+    if free < 170e9:
+        pytest.skip("needs about 160 GB of free device memory")
+    print("case largest plane", flush=True)
+    nx, ny = 32768, 32767
+    bub = [(nx - 1000.5, ny - 800.0, 300.0), (700.0, 600.0, 200.0)]
+    p = L.make_params(nx, ny, T_over_Tc=0.7, walls=True, precision="fp32", tau_nu=0.6)
+    sim = L.Sim(p)
+    sim.init_bubble(bub, W=5.0, delta=0.02)
+    sim.set_variant(L.variant_names().index("fused2-128x16"))
+    sim.step(3)
+    sim.sync()
+    f0 = sim.populations()
+    P = oracle_params(p)
+    h, w = 32, 40
+    windows = [
+        (np.arange(ny - h, ny), np.r_[nx - w // 2:nx, 0:w // 2], False, True),     # top corner, x edge
+        (np.arange(0, h), np.arange(nx - w, nx), True, False),                     # bottom, last columns
+        (np.arange(ny - 816, ny - 816 + h), np.arange(nx - 720, nx - 720 + w), False, False),  # interface
+        (np.arange(ny // 2, ny // 2 + h), np.arange(nx // 2 - w // 2, nx // 2 + w // 2), False, False),
+    ]
+    for variant in ("fused2-128x16", "fused-64x16", "2pass-64x4"):
+        sim.set_populations(f0)
+        sim.set_variant(L.variant_names().index(variant))
+        sim.step(1)
+        sim.sync()
+        f1 = sim.populations()
+        for rows, cols, bottom, top in windows:
+            r = torch.as_tensor(rows, device=f0.device)
+            c = torch.as_tensor(cols, device=f0.device)
+            want = to_oracle(f0.index_select(1, r).index_select(2, c))
+            assert ostep.step(ostep.with_grid(P, w, h, walls=bottom or top), want, 1) == 0
+            got = to_oracle(f1.index_select(1, r).index_select(2, c))
+            sl = (slice(0 if bottom else 3, h if top else h - 3), slice(3, w - 3))
+            err = rel_inf(got[sl], want[sl])
+            print(variant, "window rows %d.. cols %d.. err %.2e" % (rows[0], cols[0], err), flush=True)
+            assert err < STEP_TOL["fp32"]
+        del f1
+    sim.close()
+    del f0
+    torch.cuda.empty_cache()

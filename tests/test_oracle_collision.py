@@ -117,3 +117,27 @@ def test_li_term_only_touches_energy_moments():
     dm = M @ d
     assert np.allclose(np.delete(dm, [1, 2]), 0, atol=1e-15)
     assert dm[1] > 0 and dm[2] < 0
+
+
+def test_each_moment_relaxes_at_its_own_rate():
+    """Eqs. 2-3 without force: a perturbation delta placed in one
+    non-conserved moment alone (f = f_eq + delta M^-1 e_k) leaves the
+    collision as (1 - s_k) delta in that moment and nothing in the others,
+    with s in the order (rho, e, zeta, jx, qx, jy, qy, pxx, pxy) of Eq. 2.
+    Distinct rates per group, so relaxing a moment at another moment's rate
+    fails."""
+    M, Minv = stepper.transform()
+    s_rho, s_e, s_z, s_j, s_q, s_nu = 1.0, 0.7, 1.3, 1.0, 1.6, 0.9
+    rates = np.array([s_rho, s_e, s_z, s_j, s_q, s_j, s_q, s_nu, s_nu])
+    P = _params(rates)
+    rng = np.random.default_rng(5)
+    for k in (1, 2, 4, 6, 7, 8):
+        rho = rng.uniform(0.05, 0.45)
+        v = rng.uniform(-0.1, 0.1, 2)
+        delta = 1e-3 * rho
+        f = textbook_feq(rho, v) + delta * Minv[:, k]
+        out = stepper.collide_node(P, f, 0.3, 0.0, 0.0)
+        dm = M @ out - stepper.equilibrium_moments(rho, v[0], v[1])
+        want = np.zeros(9)
+        want[k] = (1.0 - rates[k]) * delta
+        assert np.allclose(dm, want, rtol=0, atol=1e-15), (k, dm, want)
