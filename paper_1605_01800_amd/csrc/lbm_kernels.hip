@@ -552,16 +552,36 @@ __global__ __launch_bounds__(BLOCK) void collide_stream_kernel(const InstDev *__
 // written while another wavefront reads it, and one barrier per iteration
 // suffices.
 
+// The value of lane i + N of the same 16-lane row (a DPP row shift, a plain
+// register move: no LDS, no address arithmetic); lanes whose source lies
+// outside the row get 0.
+template <int N>
+__device__ __forceinline__ float row_next(float v)
+{
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x100 + N, 0xF, 0xF, true));
+}
+
+template <int N>
+__device__ __forceinline__ double row_next(double v)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, 0x100 + N, 0xF, 0xF, true);
+    const unsigned hi =
+        (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), 0x100 + N, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // Lanes b .. b+8 (b = 0 or 16) hold populations 0..8 of one ring column;
 // returns in lane b the column's rho - rho_ref, summed in the order of
 // density().  Every lane of the wavefront must call it.
 template <typename T>
 __device__ __forceinline__ T halo_density(T v)
 {
-    const T s1 = v + __shfl_down(v, 1);       // lane b + 2i: v2i + v2i+1
-    const T s2 = s1 + __shfl_down(s1, 2);     // lane b + 4i: pairs of pairs
-    const T s3 = s2 + __shfl_down(s2, 4);     // lane b: v0 + ... + v7
-    return s3 + __shfl_down(v, 8);
+    const T s1 = v + row_next<1>(v);          // lane b + 2i: v2i + v2i+1
+    const T s2 = s1 + row_next<2>(s1);        // lane b + 4i: pairs of pairs
+    const T s3 = s2 + row_next<4>(s2);        // lane b: v0 + ... + v7
+    return s3 + row_next<8>(v);
 }
 
 // Memory row of lattice row l (ghost rows -1 and ny mirror at walls, wrap
