@@ -13,7 +13,10 @@ Modules:
                  stability condition (Eq. 9), in mpmath
   diagnostics -- bubble radius, pressure jump, slab densities from rho fields
 
-Parity unpinned: the mirror reading of the pseudopotential at solid wall
-sites, the bubble-radius definition and the wall-pressure peak have no value in
-the paper to check against; only their agreement with the GPU path is tested.
+Parity unpinned: the bubble-radius definition and the wall-pressure peak have
+no value in the paper to check against; only their agreement with the GPU path
+is tested.  The mirror reading of the pseudopotential at solid wall sites is
+likewise not in the paper; it is pinned only through the symmetry it implies
+(for states uniform in x and at rest, each wall is a plane of mirror symmetry
+of the periodic channel twice as tall).
 """

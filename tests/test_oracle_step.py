@@ -180,3 +180,34 @@ def test_nonfinite_state_is_reported():
     rho[2, 3] = 0.99           # psi^2 < 0 next to the EOS pole
     f = stepper.init_populations(P, rho)
     assert stepper.step(P, f, 1) == -4
+
+
+@pytest.mark.parametrize("gap", [9.3, 4.0])
+def test_walls_are_planes_of_mirror_symmetry(gap):
+    """Halfway bounce-back at y = -1/2 and y = ny - 1/2 with the mirrored psi
+    of the solid rows, on states uniform in x and at rest (where reversing a
+    diagonal population and reflecting it in y give the same value), must
+    reproduce the lower half of a periodic channel of 2 ny rows whose upper
+    half is the mirror image of the lower: both walls are then planes of
+    symmetry of the periodic run.  A liquid layer on the lower wall, vapour,
+    and a thinner layer on the upper wall; pins the wall position, the
+    bounce-back of every population and the psi mirror against the periodic
+    path."""
+    nx, ny = 3, 24
+    y = np.arange(ny)
+    mid, half = 0.5 * (RL07 + RG07), 0.5 * (RL07 - RG07)
+    col = mid - half * np.tanh(2 * (y - gap) / 5.0) * np.tanh(2 * (ny - 4.5 - y) / 5.0)
+    Pw = stepper.make_params(nx, ny, T07, walls=True, tau_nu=0.7)
+    fw = stepper.init_populations(Pw, np.tile(col[:, None], (1, nx)))
+    Pp = stepper.make_params(nx, 2 * ny, T07, walls=False, tau_nu=0.7)
+    colp = np.concatenate([col, col[::-1]])
+    fp = stepper.init_populations(Pp, np.tile(colp[:, None], (1, nx)))
+    assert stepper.step(Pw, fw, 300) == 0
+    assert stepper.step(Pp, fp, 300) == 0
+    assert np.max(np.abs(fw - fp[:ny])) < 1e-13 * np.max(np.abs(fw))
+    # the periodic run itself stays mirror symmetric (y -> 2 ny - 1 - y, e_y -> -e_y)
+    refl = [0, 1, 4, 3, 2, 8, 7, 6, 5]
+    assert np.max(np.abs(fp[ny:][::-1][:, :, refl] - fp[:ny])) < 1e-13 * np.max(np.abs(fw))
+    # and the state has moved away from the start (the test is not vacuous)
+    f0 = stepper.init_populations(Pw, np.tile(col[:, None], (1, nx)))
+    assert np.max(np.abs(fw - f0)) > 1e-4
