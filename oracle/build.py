@@ -25,8 +25,9 @@ def build(verbose=False):
 
 
 def ensure_built():
-    """Builds the oracle only when no built library is present."""
-    if not os.path.exists(LIB):
+    """Builds the oracle when no built library is present or the source is
+    newer than it."""
+    if not os.path.exists(LIB) or os.path.getmtime(SRC) > os.path.getmtime(LIB):
         build()
     return LIB
 
