@@ -204,6 +204,13 @@ int lbm_batch_step_each(void *batch, const int64_t *counts, int n_counts);
 int lbm_batch_size(void *batch, int *n_attached);
 /* Non-blocking completion query of the batch's stream, as lbm_poll. */
 int lbm_batch_poll(void *batch, int *done);
+/* The non-finite latch of every attached instance as of the end of the last
+ * chunk the batch stepped, in attach order, read in one transfer after the
+ * batch's stream has drained: nonfinite[i] = 1 for a latched instance (which
+ * then refuses further steps, alone or in a batch, until it is
+ * re-initialised), 0 otherwise.  n is the length of nonfinite and must be at
+ * least lbm_batch_size.  Synchronises the batch's stream. */
+int lbm_batch_status(void *batch, int *nonfinite, int n);
 void lbm_batch_destroy(void *batch);
 
 /* ---- kernel variants and measurement -------------------------------------- */

@@ -172,6 +172,7 @@ struct Batch {
     int64_t max_tiles;
     InstDev *d_descs;
     Tile *d_tiles;
+    int *d_status;                // latch of each member at the last chunk end
     std::vector<Instance *> members;
     std::vector<InstDev> descs;   // host copies in attach order
     int ntiles = 0;
@@ -298,7 +299,7 @@ int sync_own(Instance *h, int v = -1)
 
 // Enqueues one chunk: K steps of both passes and the end-of-chunk kernel.
 int enqueue_chunk(int prec, int variant, const InstDev *d_inst, int ninst, const Tile *d_tiles,
-                  int ntiles, int K, hipStream_t st)
+                  int ntiles, int K, hipStream_t st, int *d_status)
 {
     for (int s = 0; s < K; ++s) {
         if (kVariants[variant].fused == 2) {
@@ -310,21 +311,21 @@ int enqueue_chunk(int prec, int variant, const InstDev *d_inst, int ninst, const
             TRYHIP(launch_collide_stream(prec, variant, d_inst, d_tiles, ntiles, s, st));
         }
     }
-    TRYHIP(launch_chunk_end(d_inst, ninst, st));
+    TRYHIP(launch_chunk_end(d_inst, ninst, st, d_status));
     return LBM_OK;
 }
 
 // Runs one chunk through a cached graph when the stream can be captured.
 int run_chunk(std::map<GraphKey, hipGraphExec_t> &cache, int prec, int variant, const InstDev *d_inst,
-              int ninst, const Tile *d_tiles, int ntiles, int K, hipStream_t st)
+              int ninst, const Tile *d_tiles, int ntiles, int K, hipStream_t st, int *d_status = nullptr)
 {
-    if (st == nullptr) return enqueue_chunk(prec, variant, d_inst, ninst, d_tiles, ntiles, K, st);
+    if (st == nullptr) return enqueue_chunk(prec, variant, d_inst, ninst, d_tiles, ntiles, K, st, d_status);
     GraphKey key{variant, K, ntiles, ninst};
     auto it = cache.find(key);
     if (it == cache.end()) {
         hipGraph_t g = nullptr;
         TRYHIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        int rc = enqueue_chunk(prec, variant, d_inst, ninst, d_tiles, ntiles, K, st);
+        int rc = enqueue_chunk(prec, variant, d_inst, ninst, d_tiles, ntiles, K, st, d_status);
         hipError_t e = hipStreamEndCapture(st, &g);
         if (rc != LBM_OK) {
             if (g) (void)hipGraphDestroy(g);
@@ -384,6 +385,8 @@ int batch_sync(Batch *b)
         }
         if ((int64_t)tl.size() > b->max_tiles) return LBM_ENOMEM;
         b->ntiles = (int)tl.size();
+        // the latch copies belong to the old composition
+        TRYHIP(hipMemsetAsync(b->d_status, 0, sizeof(int) * (size_t)b->max_inst, b->stream));
         if (!tl.empty()) TRY(b->stager_tiles.upload(b->d_tiles, tl.data(), sizeof(Tile) * tl.size(), b->stream));
         b->dirty = false;
     } else {
@@ -423,7 +426,7 @@ int batch_run(Batch *b, const std::vector<int64_t> &counts, bool timed, float *m
         if (rc != LBM_OK) break;
         if (!timed) {
             rc = run_chunk(b->graphs, b->precision, b->variant, b->d_descs, n, b->d_tiles, b->ntiles, K,
-                           b->stream);
+                           b->stream, b->d_status);
         } else {
             const bool fused = kVariants[b->variant].fused;
             for (int s = 0; s < K && rc == LBM_OK && fused; ++s) {
@@ -455,7 +458,7 @@ int batch_run(Batch *b, const std::vector<int64_t> &counts, bool timed, float *m
                 if (rc == LBM_OK) rc = hip_ok(hipEventElapsedTime(&t, e0, e1));
                 if (rc == LBM_OK) ms[1] += t;
             }
-            if (rc == LBM_OK) rc = hip_ok(launch_chunk_end(b->d_descs, n, b->stream));
+            if (rc == LBM_OK) rc = hip_ok(launch_chunk_end(b->d_descs, n, b->stream, b->d_status));
         }
         if (rc != LBM_OK) break;
         for (int i = 0; i < n; ++i) {
@@ -893,7 +896,8 @@ int lbm_batch_workspace_bytes(int max_instances, int64_t max_tiles, size_t *byte
 {
     if (max_instances < 1 || max_tiles < 1 || !bytes) return LBM_EINVAL;
     *bytes = round_up(sizeof(InstDev) * (size_t)max_instances, ALIGN) +
-             round_up(sizeof(Tile) * (size_t)max_tiles, ALIGN);
+             round_up(sizeof(Tile) * (size_t)max_tiles, ALIGN) +
+             round_up(sizeof(int) * (size_t)max_instances, ALIGN);
     return LBM_OK;
 }
 
@@ -912,6 +916,11 @@ int lbm_batch_create(int precision, int max_instances, int64_t max_tiles, void *
     b->max_tiles = max_tiles;
     b->d_descs = (InstDev *)d_workspace;
     b->d_tiles = (Tile *)((char *)d_workspace + round_up(sizeof(InstDev) * (size_t)max_instances, ALIGN));
+    b->d_status = (int *)((char *)b->d_tiles + round_up(sizeof(Tile) * (size_t)max_tiles, ALIGN));
+    if (hipMemsetAsync(b->d_status, 0, sizeof(int) * (size_t)max_instances, b->stream) != hipSuccess) {
+        delete b;
+        return LBM_EHIP;
+    }
     if (b->stager_desc.init(sizeof(InstDev) * (size_t)max_instances) != LBM_OK ||
         b->stager_tiles.init(sizeof(Tile) * (size_t)max_tiles) != LBM_OK) {
         b->stager_desc.release();
@@ -959,6 +968,21 @@ int lbm_batch_size(void *batch, int *n_attached)
     Batch *b = (Batch *)batch;
     if (!b || !n_attached) return LBM_EINVAL;
     *n_attached = (int)b->members.size();
+    return LBM_OK;
+}
+
+int lbm_batch_status(void *batch, int *nonfinite, int n)
+{
+    Batch *b = (Batch *)batch;
+    if (!b || !nonfinite || n < (int)b->members.size()) return LBM_EINVAL;
+    const int m = (int)b->members.size();
+    if (m == 0) return LBM_OK;
+    TRYHIP(hipMemcpyAsync(nonfinite, b->d_status, sizeof(int) * (size_t)m, hipMemcpyDeviceToHost, b->stream));
+    TRYHIP(hipStreamSynchronize(b->stream));
+    for (int i = 0; i < m; ++i) {
+        nonfinite[i] = nonfinite[i] != 0;
+        if (nonfinite[i]) b->members[i]->sticky = LBM_ENONFINITE;
+    }
     return LBM_OK;
 }
 

@@ -106,7 +106,9 @@ hipError_t launch_fused(int prec, int variant, const InstDev *d_inst, const Tile
                         int s, hipStream_t st);
 hipError_t launch_fused2(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles, int ntiles,
                          int s, hipStream_t st);
-hipError_t launch_chunk_end(const InstDev *d_inst, int ninst, hipStream_t st);
+// End of a chunk: folds the wall-pressure maxima, advances step and parity;
+// with d_status, also copies each instance's latch to d_status[k].
+hipError_t launch_chunk_end(const InstDev *d_inst, int ninst, hipStream_t st, int *d_status = nullptr);
 hipError_t launch_init(int prec, const InstDev *d_inst, int slab_rows, const lbm_bubble *b, int nb,
                        double rho_l, double rho_g, double W, double delta, double noise_amp,
                        uint64_t seed, long long nsites, hipStream_t st);

@@ -982,11 +982,12 @@ __global__ __launch_bounds__(BLOCK) void fused2_kernel(const InstDev *__restrict
 // ---------------------------------------------------------------------------
 // end of a chunk: fold the per-step wall maxima, advance step counter/parity
 // ---------------------------------------------------------------------------
-__global__ void chunk_end_kernel(InstDev *insts, int ninst)
+__global__ void chunk_end_kernel(InstDev *insts, int ninst, int *status)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= ninst) return;
     InstDev &d = insts[k];
+    if (status) status[k] = d.flag[0];          // the batch's copy of every latch
     const int n = d.n_chunk;
     if (n <= 0) return;
     if (d.walls) {
@@ -1344,10 +1345,10 @@ hipError_t launch_fused2(int prec, int variant, const InstDev *d_inst, const Til
     return fused2_dispatch<float, true>(variant, d_inst, d_tiles, ntiles, s, st);
 }
 
-hipError_t launch_chunk_end(const InstDev *d_inst, int ninst, hipStream_t st)
+hipError_t launch_chunk_end(const InstDev *d_inst, int ninst, hipStream_t st, int *d_status)
 {
     if (ninst <= 0) return hipSuccess;
-    chunk_end_kernel<<<(ninst + 63) / 64, 64, 0, st>>>(const_cast<InstDev *>(d_inst), ninst);
+    chunk_end_kernel<<<(ninst + 63) / 64, 64, 0, st>>>(const_cast<InstDev *>(d_inst), ninst, d_status);
     return hipGetLastError();
 }
 

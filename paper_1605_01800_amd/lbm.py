@@ -100,6 +100,7 @@ _SIGS = {
     "lbm_batch_step_timed": [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_float)],
     "lbm_batch_size": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)],
     "lbm_batch_poll": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)],
+    "lbm_batch_status": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int],
     "lbm_batch_destroy": [ctypes.c_void_p],
     "lbm_batch_set_variant": [ctypes.c_void_p, ctypes.c_int],
     "lbm_batch_autotune": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
@@ -283,15 +284,26 @@ class Sim:
     def sync(self):
         _check(lib().lbm_sync(self.h), "lbm_sync")
 
+    def failed(self):
+        """Waits for the instance's work and tells whether its state has
+        turned non-finite (the latch of lbm_sync)."""
+        try:
+            self.sync()
+        except NonFiniteError:
+            return True
+        return False
+
     def poll(self):
         """True when all work enqueued for this instance has finished."""
         done = ctypes.c_int()
         _check(lib().lbm_poll(self.h, ctypes.byref(done)), "lbm_poll")
         return bool(done.value)
 
-    def macros(self, fields=True):
+    def macros(self, fields=True, check=True):
         """dict with rho, ux, uy (population precision), p (float64) tensors of
-        shape (ny, nx) when fields is true, and the diagnostics."""
+        shape (ny, nx) when fields is true, and the diagnostics.  With check
+        false a latched non-finite state is reported in diag["nonfinite"]
+        instead of raising NonFiniteError."""
         out = {}
         ptrs = [None] * 4
         if fields:
@@ -300,7 +312,9 @@ class Sim:
                     out[k] = torch.empty((self.ny, self.nx), dtype=dt, device=self.device)
             ptrs = [out[k].data_ptr() for k in ("rho", "ux", "uy", "p")]
         d = Diag()
-        _check(lib().lbm_macros(self.h, *ptrs, ctypes.byref(d)), "lbm_macros")
+        rc = lib().lbm_macros(self.h, *ptrs, ctypes.byref(d))
+        if rc != -4 or check:
+            _check(rc, "lbm_macros")
         out["diag"] = d.to_dict()
         return out
 
@@ -403,6 +417,14 @@ class Batch:
 
     def sync(self):
         self.stream.synchronize()
+
+    def status(self):
+        """Non-finite latch of every attached instance (attach order) as of the
+        last chunk end, read in one transfer; synchronises the batch."""
+        n = len(self.members)
+        arr = (ctypes.c_int * max(n, 1))()
+        _check(lib().lbm_batch_status(self.b, arr, max(n, 1)), "lbm_batch_status")
+        return [bool(arr[i]) for i in range(n)]
 
     def poll(self):
         """True when all work enqueued on the batch's stream has finished."""

@@ -13,6 +13,9 @@ compute each instance independently).
 
 The control loop only schedules; all stepping goes through the backend (the
 GPU backend below drives liblbm; tests can substitute a counting backend).
+A request whose state turns non-finite (psi^2 < 0 or an overflow, latched on
+the device) is retired at the end of the chunk in which it is seen, marked
+failed; the others continue unaffected.
 """
 import json
 import math
@@ -53,6 +56,7 @@ class Result:
     footprint: int
     diag: dict = field(default_factory=dict)
     state: object = None
+    failed: bool = False         # turned non-finite; retired at the chunk where it was seen
 
     @property
     def latency(self):
@@ -83,6 +87,7 @@ class GpuBackend:
         self.variant = variant
         if variant is not None:
             self.batch.set_variant(variant)
+        self._bad = {}
 
     def params(self, req):
         return self.lbm.make_params(req.nx, req.ny, T_over_Tc=req.T_over_Tc, walls=req.walls,
@@ -106,11 +111,15 @@ class GpuBackend:
         self.batch.step_each(counts)
 
     def sync(self):
-        self.batch.sync()
+        # one transfer reads every resident request's latch
+        self._bad = {id(m): bad for m, bad in zip(self.batch.members, self.batch.status())}
+
+    def failed(self, h):
+        return self._bad.get(id(h), False)
 
     def finish(self, h):
-        out = h.macros(fields=False)["diag"]
-        state = h.populations().cpu() if self.keep_state else None
+        out = h.macros(fields=False, check=False)["diag"]
+        state = h.populations().cpu() if self.keep_state and not out["nonfinite"] else None
         self.batch.detach(h)
         h.close()
         return out, state
@@ -163,6 +172,7 @@ class Server:
         t0 = self.clock()
         now = lambda: self.clock() - t0
         updates = 0
+        failures = 0
         busy = 0.0
         staged = []                     # prepared, attached at the next chunk boundary
 
@@ -209,19 +219,25 @@ class Server:
             still = []
             for c, a in zip(counts, active):
                 a[2] -= c
-                if a[2] == 0:
+                # a request whose state turned non-finite is retired now, so
+                # that it neither wastes steps nor stops the batch
+                bad = self.backend.failed(a[1])
+                if a[2] == 0 or bad:
                     diag, state = self.backend.finish(a[1])
                     a[3].finish = t_done
                     a[3].diag = diag
                     a[3].state = state
+                    a[3].failed = bad
                     resident -= a[3].footprint
                     results.append(a[3])
+                    if bad:
+                        failures += 1
                     if self.log is not None:
                         self.log.write(json.dumps({
                             "id": a[3].id, "arrival": a[3].arrival, "admit": a[3].admit,
                             "first_chunk": a[3].first_chunk, "finish": a[3].finish,
                             "sites": a[3].sites, "steps": a[3].steps, "footprint": a[3].footprint,
-                            "latency": a[3].latency, "diag": diag}) + "\n")
+                            "latency": a[3].latency, "failed": bad, "diag": diag}) + "\n")
                 else:
                     still.append(a)
             active = still
@@ -232,7 +248,8 @@ class Server:
                  "busy_mlups": updates / busy / 1e6 if busy > 0 else 0.0,
                  "p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99),
                  "mean_s": sum(lat) / len(lat) if lat else float("nan"),
-                 "peak_resident_bytes": self.peak_resident, "peak_slots": self.peak_slots}
+                 "peak_resident_bytes": self.peak_resident, "peak_slots": self.peak_slots,
+                 "failed": failures}
         return sorted(results, key=lambda r: r.id), stats
 
 

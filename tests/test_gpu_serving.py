@@ -44,3 +44,31 @@ def test_served_results_equal_alone_bitwise(budget_mb):
         assert r.diag["step"] == q.steps
         assert torch.equal(r.state, ref), q.id
         assert r.diag["radius"] == d["radius"]
+
+
+def test_a_failing_request_is_isolated():
+    """A request whose liquid is compressed past the point where Eq. 13 has a
+    real psi (rho_l (1 + delta) with delta = 1.5) turns non-finite in its
+    first step; it is retired after its first chunk, marked failed, and the
+    other requests finish bitwise as when stepped alone."""
+    variant = L.variant_names().index("fused-64x16")
+    reqs = _requests()[:3] + [
+        Request(id=5, nx=90, ny=70, walls=True, T_over_Tc=0.7, steps=900, bubbles=[(44.5, 25.0, 12.0)],
+                delta=1.5, arrival=0.0)]
+    be = GpuBackend(precision="fp32", max_instances=8, max_tiles=1 << 14, variant=variant, keep_state=True)
+    srv = Server(be, budget_bytes=10 ** 9, max_slots=8, chunk_steps=128)
+    results, stats = srv.run(reqs)
+    be.close()
+    assert stats["failed"] == 1
+    bad = [r for r in results if r.id == 5][0]
+    assert bad.failed and bad.diag["nonfinite"] and bad.state is None
+    assert bad.diag["step"] == 128                    # retired after its first chunk
+    for r, q in zip(sorted(results, key=lambda r: r.id)[:3], reqs[:3]):
+        assert not r.failed
+        p = L.make_params(q.nx, q.ny, T_over_Tc=q.T_over_Tc, walls=q.walls, precision="fp32", tau_nu=q.tau_nu)
+        s = L.Sim(p)
+        s.set_variant(variant)
+        s.init_bubble(q.bubbles, W=q.W, delta=q.delta)
+        s.step(q.steps)
+        assert torch.equal(r.state, s.populations().cpu()), q.id
+        s.close()

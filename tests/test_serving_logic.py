@@ -53,6 +53,9 @@ class CountingBackend:
     def sync(self):
         pass
 
+    def failed(self, h):
+        return False
+
     def finish(self, h):
         self.attached.remove(h)
         self.resident -= self.footprint(h["req"])
@@ -138,3 +141,30 @@ def test_request_trace_matches_the_served_workload():
             assert 0.005 <= t["delta"] <= 0.03
     frac = sum(t["walls"] for t in tr) / 512
     assert 0.4 < frac < 0.6
+
+
+class FailingBackend(CountingBackend):
+    """Marks the requests in `bad` as non-finite once they have been stepped."""
+
+    def __init__(self, clock, bad):
+        super().__init__(clock)
+        self.bad = set(bad)
+
+    def failed(self, h):
+        return h["req"].id in self.bad and self.steps_done.get(h["req"].id, 0) > 0
+
+
+def test_failed_requests_are_retired_after_their_first_chunk():
+    clock = FakeClock()
+    be = FailingBackend(clock, bad={3, 7})
+    reqs = _trace(20, rate=5.0)
+    srv = Server(be, budget_bytes=10 ** 10, chunk_steps=500, clock=clock, sleep=clock.sleep)
+    results, stats = srv.run(reqs)
+    assert len(results) == 20 and stats["failed"] == 2
+    for r, q in zip(results, sorted(reqs, key=lambda q: q.id)):
+        if q.id in (3, 7):
+            assert r.failed and r.diag["step"] == 500 < q.steps
+        else:
+            assert not r.failed and r.diag["step"] == q.steps
+    assert stats["site_updates"] == sum(q.sites * (500 if q.id in (3, 7) else q.steps) for q in reqs)
+    assert be.resident == 0
