@@ -63,7 +63,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="laplace_sweep",
                     choices=["laplace_sweep", "collapse_large", "precision_large", "collapse_horizon",
                              "laplace_physics", "coexistence_sweep", "critical_nucleus", "paper_collapse",
@@ -320,16 +320,26 @@ def main():
     print("# workload %s sites %d variant %s" % (args.workload, sites, workload["tile"]),
           file=sys.stderr, flush=True)
 
-    batch.step(args.warmup)
+    # The timed steps run as five equal parts with events between them (the
+    # whole region gives `value`; the parts give a median), the warm-up in
+    # pieces of the same size so that their graphs are captured beforehand.
+    part = args.steps // 5 if args.steps % 5 == 0 and args.warmup >= args.steps // 5 else args.steps
+    done = 0
+    while done < args.warmup:
+        n = min(part, args.warmup - done)
+        batch.step(n)
+        done += n
     batch.sync()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps // part + 1)]
     torch.cuda.synchronize()
-    e0.record(batch.stream)
-    batch.step(args.steps)
-    e1.record(batch.stream)
-    e1.synchronize()
-    ms = e0.elapsed_time(e1)
+    ev[0].record(batch.stream)
+    for i in range(1, len(ev)):
+        batch.step(part)
+        ev[i].record(batch.stream)
+    ev[-1].synchronize()
+    ms = ev[0].elapsed_time(ev[-1])
+    part_ms = sorted(ev[i - 1].elapsed_time(ev[i]) / part for i in range(1, len(ev)))
+    median_ms = part_ms[len(part_ms) // 2]
     torch.cuda.synchronize()
     for s in sims:
         s.sync()                          # raises if a non-finite value was latched
@@ -374,6 +384,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms / args.steps,
+        "ms_per_step_median_of_parts": median_ms,
+        "timed_parts": len(part_ms),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
