@@ -337,33 +337,28 @@ __device__ __forceinline__ void collide_site(T f[9], T psi_c, T Fx, T Fy, const 
 
     // equilibria, Eq. 4 (e and zeta rows shifted by 2 rho_ref and -rho_ref,
     // like m1 and m2: rho (-2 + 3 v^2) + 2 rho_ref, rho (1 - 3 v^2) - rho_ref)
-    const T e1 = T(3) * rho * v2 - T(2) * dm;
-    const T e2 = dm - T(3) * rho * v2;
-    const T e4 = -rho * vx;
-    const T e6 = -rho * vy;
+    const T rv2 = T(3) * rho * v2;
+    const T e1 = rv2 - T(2) * dm;
+    const T e2 = dm - rv2;
+    const T rvx = rho * vx, rvy = rho * vy;   // e4 = -rvx, e6 = -rvy
     const T e7 = rho * (vx * vx - vy * vy);
-    const T e8 = rho * vx * vy;
+    const T e8 = rvx * vy;
 
-    // (I - Lambda/2) S with S of Eq. 14; for the e and zeta rows
-    // (1 - s/2) / (tau - 1/2) = s, so Li's term enters as s 0.75 eps |F|^2 / psi^2.
+    // Relaxation, Eq. 3, with the source (I - Lambda/2) S of Eq. 14 and the
+    // scale of the inverse transform folded into per-instance constants:
+    // a_k = c_k m*_k = (1 - s_k) c_k m_k + s_k c_k m_eq_k + c_k (1 - s_k/2) S_k.
+    // For the e and zeta rows (1 - s/2) / (tau - 1/2) = s, so Li's term enters
+    // as s 0.75 eps |F|^2 / psi^2.  rho and j are collision invariants up to
+    // the source: m0* = rho (dm in shifted form), m3* = jx + Fx, m5* = jy + Fy
+    // for any s_rho, s_j.
     const T vF = vx * Fx + vy * Fy;
     const T li = (Fx * Fx + Fy * Fy) * recip(psi_c * psi_c);
-    const T q1 = R.h_e * T(6) * vF + R.li_e * li;
-    const T q2 = -R.h_z * T(6) * vF - R.li_z * li;
-    const T q4 = -R.h_q * Fx;
-    const T q6 = -R.h_q * Fy;
-    const T q7 = R.h_nu * T(2) * (vx * Fx - vy * Fy);
-    const T q8 = R.h_nu * (vx * Fy + vy * Fx);
-
-    // relaxation, Eq. 3.  rho and j are collision invariants up to the
-    // source: m0* = rho (dm in shifted form), m3* = jx + Fx, m5* = jy + Fy for
-    // any s_rho, s_j.
-    const T n1 = m1 - R.s_e * (m1 - e1) + q1;
-    const T n2 = m2 - R.s_z * (m2 - e2) + q2;
-    const T n4 = m4 - R.s_q * (m4 - e4) + q4;
-    const T n6 = m6 - R.s_q * (m6 - e6) + q6;
-    const T n7 = m7 - R.s_nu * (m7 - e7) + q7;
-    const T n8 = m8 - R.s_nu * (m8 - e8) + q8;
+    const T a1 = R.e_m * m1 + R.e_eq * e1 + R.e_vf * vF + R.e_li * li;
+    const T a2 = R.z_m * m2 + R.z_eq * e2 + R.z_vf * vF + R.z_li * li;
+    const T a4 = R.q_m * m4 - R.q_eq * rvx + R.q_f * Fx;
+    const T a6 = R.q_m * m6 - R.q_eq * rvy + R.q_f * Fy;
+    const T a7 = R.n_m * m7 + R.n_eq * e7 + R.n_xx * (vx * Fx - vy * Fy);
+    const T a8 = R.n_m * m8 + R.n_eq * e8 + R.n_xy * (vx * Fy + vy * Fx);
 
     // f* = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m*.
     // The conserved moments are divided, not multiplied by a rounded
@@ -374,14 +369,8 @@ __device__ __forceinline__ void collide_site(T f[9], T psi_c, T Fx, T Fy, const 
     // quotient (div9, div6) has no such bias.  The other moments relax, so a
     // bias there does not accumulate.
     const T a0 = div9(dm);
-    const T a1 = n1 * T(1.0 / 36.0);
-    const T a2 = n2 * T(1.0 / 36.0);
     const T a3 = div6(jx + Fx);
-    const T a4 = n4 * T(1.0 / 12.0);
     const T a5 = div6(jy + Fy);
-    const T a6 = n6 * T(1.0 / 12.0);
-    const T a7 = n7 * T(0.25);
-    const T a8 = n8 * T(0.25);
 
     const T ax = a0 - a1 - T(2) * a2;       // common part of the axis populations
     const T dg = a0 + T(2) * a1 + a2;       // common part of the diagonals
