@@ -353,6 +353,12 @@ class Sim:
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
+            # lbm_destroy detaches the instance from its batch (after the
+            # batch's pending work); keep the binding's view in step
+            b = getattr(self, "_batch", None)
+            if b is not None and self in b.members:
+                b.members.remove(self)
+            self._batch = None
             lib().lbm_destroy(self.h)
             self.h = ctypes.c_void_p()
 
