@@ -37,6 +37,18 @@ BYTES_COLLIDE = {4: 9 * 4 + 4 + 9 * 4, 8: 9 * 8 + 8 + 9 * 8}
 BYTES_FUSED = {4: 18 * 4, 8: 18 * 8}
 
 
+def timing_part(steps, warmup):
+    """Steps per timed part: the largest divisor of `steps` between steps / 20
+    and steps / 5 (5 to 20 parts for a median) that is at most `warmup` (so
+    that the warm-up captures the part's graph before the timed region); else
+    the largest divisor up to `warmup`; `steps` without a warm-up."""
+    if warmup < 1:
+        return steps
+    divisors = [d for d in range(1, steps + 1) if steps % d == 0 and d <= warmup]
+    small = [d for d in divisors if 5 * d <= steps and 20 * d >= steps]
+    return max(small) if small else max(divisors)
+
+
 def measured_traffic(workload, variant_name):
     """HBM bytes per launch of the dominant kernel from the rocprofv3 FETCH_SIZE
     and WRITE_SIZE counters recorded in profiles/traffic.json (each scaled by
@@ -323,7 +335,7 @@ def main():
     # The timed steps run as five equal parts with events between them (the
     # whole region gives `value`; the parts give a median), the warm-up in
     # pieces of the same size so that their graphs are captured beforehand.
-    part = args.steps // 5 if args.steps % 5 == 0 and args.warmup >= args.steps // 5 else args.steps
+    part = timing_part(args.steps, args.warmup)
     done = 0
     while done < args.warmup:
         n = min(part, args.warmup - done)
