@@ -77,7 +77,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="laplace_sweep",
-                    choices=["laplace_sweep", "collapse_large", "precision_large", "collapse_horizon",
+                    choices=["laplace_sweep", "collapse_large", "collapse_shard", "precision_large",
+                             "collapse_horizon",
                              "laplace_physics", "coexistence_sweep", "critical_nucleus", "paper_collapse",
                              "single_small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -131,6 +132,21 @@ def collapse_large_sims(L, precision, device):
     p = L.make_params(nx, ny, T_over_Tc=0.6, walls=True, precision=precision, tau_nu=0.51)
     s = L.Sim(p, device=device)
     s.init_bubble(bub, W=5.0, delta=0.02)
+    return [s]
+
+
+def collapse_shard_sims(L, precision, device):
+    """One GPU's share of the 8192 x 4096 grid split in y over 8 GPUs: the
+    lowest 512 rows (lower wall; the cut at the top would exchange a halo
+    with the next GPU and is a wall here), with the part of the largest
+    disc that falls into them."""
+    from paper_1605_01800_amd import inputs
+    nx, ny = 8192, 4096
+    bub = inputs.non_overlapping_discs(nx, ny, [300, 200, 150], W=5.0, seed=0, walls=True)
+    inside = [b for b in bub if b[1] - b[2] < 512]
+    p = L.make_params(nx, 512, T_over_Tc=0.6, walls=True, precision=precision, tau_nu=0.6)
+    s = L.Sim(p, device=device)
+    s.init_bubble(inside or [(4095.5, 255.5, 150.0)], W=5.0, delta=0.02)
     return [s]
 
 
@@ -313,6 +329,11 @@ def main():
         workload = {"workload": "laplace_sweep", "instances": len(sims), "grid": "256x256",
                     "periodic": True, "T_over_Tc": [0.6, 0.7, 0.8, 0.9], "radii": [20, 30, 40, 50, 60],
                     "slab_rows": 128, "tau_nu": 0.6, "eps": 1.86}
+    elif args.workload == "collapse_shard":
+        sims = collapse_shard_sims(L, precision, device)
+        workload = {"workload": "collapse_shard", "instances": 1, "grid": "8192x512",
+                    "shard_of": "8192x4096 over 8 GPUs (rows 0-511, lower wall)", "walls_y": True,
+                    "T_over_Tc": 0.6, "delta": 0.02, "tau_nu": 0.6, "eps": 1.86}
     else:
         sims = collapse_large_sims(L, precision, device)
         workload = {"workload": "collapse_large", "instances": 1, "grid": "8192x4096",
