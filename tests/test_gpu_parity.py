@@ -336,3 +336,31 @@ def test_poll_reports_completion():
     assert sim.diag()["step"] == 1000
     b.close()
     sim.close()
+
+
+def test_empty_and_zero_step_calls_are_no_ops():
+    """An empty batch steps without error; zero steps, alone or per instance
+    in a batch, leave the state and the step counter bitwise unchanged."""
+    print("case empty", flush=True)
+    p = L.make_params(70, 33, T_over_Tc=0.7, walls=True, precision="fp32", tau_nu=0.6)
+    empty = L.Batch(precision="fp32", max_instances=2, max_tiles=64)
+    empty.step(10)
+    empty.sync()
+    assert empty.status() == [] and empty.poll()
+    sim = L.Sim(p).init_bubble([(34.5, 12.0, 6.0)], W=4.0, delta=0.01)
+    sim.step(5)
+    before = sim.populations()
+    sim.step(0)
+    assert torch.equal(before, sim.populations()) and sim.diag()["step"] == 5
+    other = L.Sim(p).init_bubble([(20.5, 20.0, 5.0)], W=4.0)
+    b = L.Batch(precision="fp32", max_instances=2, max_tiles=2 * L.tile_count(p))
+    b.attach(sim)
+    b.attach(other)
+    b.step_each([0, 7])
+    b.sync()
+    assert torch.equal(before, sim.populations()) and sim.diag()["step"] == 5
+    assert other.diag()["step"] == 7
+    b.close()
+    empty.close()
+    sim.close()
+    other.close()
