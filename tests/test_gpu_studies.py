@@ -84,3 +84,19 @@ def test_paper_collapse_dumbbell_then_split():
     assert split["waist"] == 0
     # densities stay below the limit where Eq. 13 has a real psi
     assert max(x["rho_max"] for x in h) < out["rho_psi_limit"]
+
+
+def test_laplace_sweep_tension_falls_with_temperature():
+    """The 24-instance sweep (Section 3.1, Fig. 3) in binary32: for every
+    temperature the pressure jump is a straight line in 1/R, the surface
+    tension falls from 0.6 to 0.9 T_c, and the slab densities sit on the
+    Maxwell liquid branch (1e-3) and within 10 % of its gas branch."""
+    out = studies.laplace_physics("cuda:0", steps=24000)
+    t = out["temperatures"]
+    sig = [t[k]["sigma"] for k in ("0.6", "0.7", "0.8", "0.9")]
+    print(sig, [t[k]["r2"] for k in t], [t[k]["dissolved_initial_radii"] for k in t])
+    assert all(a > b > 0 for a, b in zip(sig, sig[1:]))
+    for k, e in t.items():
+        assert len(e["radii"]) >= 3 and e["r2"] > 0.95, k
+        assert abs(e["rho_l_rel_dev"]) < 1e-3, k
+        assert abs(e["rho_g_rel_dev"]) < 0.10, k
