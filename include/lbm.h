@@ -132,7 +132,9 @@ int lbm_init_bubble(void *handle, const lbm_bubble *b, int nb, int slab_rows,
  * the step counter, the wall-pressure peak and the non-finite latch. */
 int lbm_init_density(void *handle, const void *d_rho, double rho_l, double rho_g);
 
-/* Enqueues n >= 0 timesteps (Eqs. 15, 13, 7, 6, 4, 14, 3, 5).  Asynchronous. */
+/* Enqueues n >= 0 timesteps (Eqs. 15, 13, 7, 6, 4, 14, 3, 5).  Asynchronous.
+ * LBM_ESTATE while the handle is attached to a batch (step the batch) or has
+ * no state yet; LBM_ENONFINITE once the latch has been read as set. */
 int lbm_step(void *handle, int64_t n);
 
 /* Macroscopic fields of the current state and the diagnostics.  d_rho, d_ux,
@@ -195,7 +197,9 @@ int lbm_batch_create(int precision, int max_instances, int64_t max_tiles, void *
                      size_t ws_bytes, void *hip_stream, void **batch);
 int lbm_batch_attach(void *batch, void *handle);
 int lbm_batch_detach(void *batch, void *handle);
-/* n steps of every attached instance.  Asynchronous. */
+/* n steps of every attached instance.  Asynchronous.  LBM_ENONFINITE, with
+ * nothing enqueued, if an instance that would step has a latched non-finite
+ * state (detach it first). */
 int lbm_batch_step(void *batch, int64_t n);
 /* Same, for a per-instance count: counts[i] steps for the i-th attached
  * instance (attach order); instances with fewer steps finish first and stay
@@ -233,8 +237,9 @@ int lbm_batch_set_variant(void *batch, int variant);
  * state or before initialising). */
 int lbm_batch_autotune(void *batch, int reps, int *best_variant, float *ms_per_step);
 /* Runs n steps of the batch with a HIP event pair around every kernel launch
- * and returns the summed device time per kernel kind: ms[0] density/psi pass,
- * ms[1] force+collide+stream pass (ms has 2 entries). */
+ * and returns the summed device time per kernel kind (ms has 2 entries):
+ * two-pass variants ms[0] density/psi pass, ms[1] force+collide+stream pass;
+ * single-pass variants ms[0] = 0, ms[1] the whole step. */
 int lbm_batch_step_timed(void *batch, int64_t n, float *ms);
 int lbm_step_timed(void *handle, int64_t n, float *ms);
 
