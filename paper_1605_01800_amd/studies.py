@@ -347,7 +347,7 @@ def cs_pressure(rho, T, a=0.5, b=4.0, R=1.0):
     return rho * R * T * (1 + eta + eta * eta - eta ** 3) / (1 - eta) ** 3 - a * rho * rho
 
 
-def liquid_density_for_pressure(L, T, p_target, a=0.5, b=4.0, R=1.0):
+def liquid_density_for_pressure(T, p_target, a=0.5, b=4.0, R=1.0):
     """Density on the liquid branch (above the liquid spinodal) where the
     Carnahan-Starling pressure (Eq. 15) equals p_target, by bisection."""
     def p_eos(rho):
@@ -384,7 +384,7 @@ def critical_nucleus(device, steps, sigma, r_star=11.3, radii=None, n=401, T_ove
     T = L.temperature(T_over_Tc)
     g, l, p0 = L.maxwell(T)
     dP = sigma / r_star
-    rho_liq = liquid_density_for_pressure(L, T, p0 - dP)
+    rho_liq = liquid_density_for_pressure(T, p0 - dP)
     if radii is None:
         radii = [r_star + d for d in (-4, -3, -2, -1.5, -1, -0.5, 0.5, 1, 1.5, 2, 3, 4)]
     c = 0.5 * (n - 1)

@@ -57,9 +57,9 @@ def test_liquid_density_for_pressure_is_on_the_liquid_branch():
     from oracle import coexist
     T = coexist.temperature(0.5)
     g, l, p0 = coexist.maxwell(T)
-    rho = studies.liquid_density_for_pressure(None, T, p0)
+    rho = studies.liquid_density_for_pressure(T, p0)
     assert rho == pytest.approx(l, rel=1e-9)
-    rho2 = studies.liquid_density_for_pressure(None, T, p0 - 1e-3)
+    rho2 = studies.liquid_density_for_pressure(T, p0 - 1e-3)
     assert rho2 < l and abs(studies.cs_pressure(rho2, T) - (p0 - 1e-3)) < 1e-13
     s_g, s_l = coexist.spinodals(T)
     assert rho2 > s_l
