@@ -269,10 +269,11 @@ def laplace_physics(device, steps, n=256):
 def coexistence_sweep(device, steps, T_over_Tc=(0.5, 0.6, 0.7, 0.8, 0.9), eps=(1.0, 1.86, 2.0),
                       tau_nu=(0.51, 0.6, 0.8), nx=64, ny=256, precision="fp64"):
     """Flat liquid slabs (ny / 2 liquid rows in a periodic nx x ny box), one
-    instance per (T, eps, tau_nu), stepped together as one batch and averaged
-    over the last quarter of the run: the coexisting densities against the
-    Maxwell rule.  Instances that turn non-finite are reported as such (the
-    batch steps each instance in its own chunk, so the others go on)."""
+    instance per (T, eps, tau_nu), each stepped on its own stream in chunks of
+    1000 steps and averaged over the last quarter of the run: the coexisting
+    densities against the Maxwell rule.  An instance that turns non-finite is
+    reported with the step count at which its latch was first seen (a
+    multiple of 1000) and stops alone; the others go on."""
     from . import lbm as L
     cases, sims = [], []
     for tr in T_over_Tc:
