@@ -255,6 +255,15 @@ int lbm_critical_point(double a, double b, double R, double *T_c, double *rho_c,
 int lbm_maxwell(double a, double b, double R, double T, double *rho_g,
                 double *rho_l, double *p0);
 
+/* Coexisting densities of the lattice model with Li's term predicted by the
+ * mechanical-stability condition of Eq. 9 for a flat interface,
+ * int (p0 - p) psi' / psi^(1+eps) drho = 0 between rho_g and rho_l with
+ * p(rho_g) = p(rho_l) = p0 and psi of Eq. 13 (c = 1, c_s^2 = 1/3, G < 0).
+ * eps = 0 is the condition without Li's term.  LBM_EINVAL when no pressure
+ * satisfies it (e.g. eps = 1 below about 0.7 T_c).  Host only. */
+int lbm_mechanical_stability(double a, double b, double R, double T, double G, double eps,
+                             double *rho_g, double *rho_l, double *p0);
+
 /* Plain device-to-device copy kernel of n bytes (n a multiple of 16) on a
  * stream, for calibrating the memory-traffic counters against a known byte
  * count.  Asynchronous. */

@@ -126,3 +126,131 @@ extern "C" int lbm_maxwell(double a, double b, double R, double T, double *rho_g
     if (p0) *p0 = (double)P;
     return LBM_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Coexistence of the lattice model with Li's term: the mechanical-stability
+// condition of Eq. 9 for a flat interface,
+//   int_{rho_g}^{rho_l} (p0 - p(rho)) psi'(rho) / psi(rho)^(1+eps) drho = 0,
+// with p(rho_g) = p(rho_l) = p0 and psi of Eq. 13, psi^2 = 2 (rho/3 - p) / (-G)
+// (c = 1, c_s^2 = 1/3), so psi' = (1/3 - dp/drho) / (-G psi).
+namespace {
+
+struct Eq9 {
+    Cs cs;
+    ld mG;    // -G > 0
+    ld eps;
+    ld p0;
+    ld psi(ld rho) const { return sqrtl(2 * (rho / 3 - cs.p(rho)) / mG); }
+    // integrand in u = ln rho (d rho = rho du)
+    ld f(ld u) const
+    {
+        const ld rho = expl(u);
+        const ld s = psi(rho);
+        const ld ds = (1.0L / 3 - cs.dp(rho)) / (mG * s);
+        return (p0 - cs.p(rho)) * ds * powl(s, -1 - eps) * rho;
+    }
+};
+
+// n-point Gauss-Legendre nodes and weights on [-1, 1]: Newton's method on
+// P_n from the Chebyshev-like first guess, P_n by the three-term recurrence.
+struct GaussLegendre {
+    static const int n = 12;
+    ld x[n], w[n];
+    GaussLegendre()
+    {
+        const ld pi = 3.14159265358979323846264338327950288L;
+        for (int i = 0; i < n; ++i) {
+            ld z = cosl(pi * (i + 0.75L) / (n + 0.5L)), dP = 1;
+            for (int it = 0; it < 100; ++it) {
+                ld p0 = 1, p1 = z;
+                for (int k = 2; k <= n; ++k) {
+                    const ld p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+                    p0 = p1;
+                    p1 = p2;
+                }
+                dP = n * (z * p1 - p0) / (z * z - 1);
+                const ld dz = p1 / dP;
+                z -= dz;
+                if (fabsl(dz) < 1e-20L) break;
+            }
+            x[i] = z;
+            w[i] = 2 / ((1 - z * z) * dP * dP);
+        }
+    }
+};
+
+// Composite Gauss-Legendre over [ln rho_g, ln rho_l]: the integrand is smooth
+// there (psi > 0, and psi' stays finite through the spinodals), and ln rho
+// spreads the steep gas side over as many panels as the liquid side.
+ld eq9_integral(const Eq9 &q, ld rho_g, ld rho_l)
+{
+    static const GaussLegendre gl;
+    const ld u0 = logl(rho_g), u1 = logl(rho_l);
+    const int panels = 96;
+    const ld h = (u1 - u0) / panels;
+    ld sum = 0;
+    for (int i = 0; i < panels; ++i) {
+        const ld c = u0 + (i + 0.5L) * h;
+        ld part = 0;
+        for (int k = 0; k < GaussLegendre::n; ++k) part += gl.w[k] * q.f(c + 0.5L * h * gl.x[k]);
+        sum += 0.5L * h * part;
+    }
+    return sum;
+}
+
+}  // namespace
+
+extern "C" int lbm_mechanical_stability(double a, double b, double R, double T, double G, double eps,
+                                        double *rho_g, double *rho_l, double *p0)
+{
+    double Tc, rc;
+    if (lbm_critical_point(a, b, R, &Tc, &rc, nullptr) != LBM_OK) return LBM_EINVAL;
+    if (!(T > 0) || !(T < Tc) || !(G < 0) || !(eps >= 0)) return LBM_EINVAL;
+    Eq9 q{Cs{(ld)a, (ld)b / 4, (ld)R, (ld)T}, -(ld)G, (ld)eps, 0};
+    const Cs &cs = q.cs;
+    const ld pole = 4.0L / b;
+    const ld sg = bisect([&](ld r) { return cs.dp(r); }, 1e-12L, (ld)rc);
+    const ld sl = bisect([&](ld r) { return cs.dp(r); }, (ld)rc, pole * (1 - 1e-12L));
+    const ld p_hi = cs.p(sg);
+    // a gas root needs p0 > 0 (p -> 0+ as rho -> 0); a liquid root p0 > p(sl)
+    const ld p_lo = cs.p(sl) > 0 ? cs.p(sl) : 0;
+    auto roots = [&](ld P, ld &g, ld &l) {
+        g = bisect([&](ld r) { return cs.p(r) - P; }, 1e-300L, sg);
+        l = bisect([&](ld r) { return cs.p(r) - P; }, sl, pole * (1 - 1e-15L));
+    };
+    auto I = [&](ld P) {
+        ld g, l;
+        roots(P, g, l);
+        Eq9 qq = q;
+        qq.p0 = P;
+        return eq9_integral(qq, g, l);
+    };
+    // scan the admissible pressures (geometrically near 0) for a sign change
+    const int n = 400;
+    ld prev_p = 0, prev_i = 0;
+    bool have = false, found = false;
+    ld lo = 0, hi = 0;
+    for (int i = 1; i < n; ++i) {
+        const ld t = (ld)i / n;
+        const ld P = p_lo > 0 ? p_lo + (p_hi - p_lo) * t : p_hi * powl(1e-12L, 1 - t);
+        const ld v = I(P);
+        if (!isfinite((double)v)) continue;
+        if (have && ((v > 0) != (prev_i > 0))) {
+            lo = prev_p;
+            hi = P;
+            found = true;
+            break;
+        }
+        prev_p = P;
+        prev_i = v;
+        have = true;
+    }
+    if (!found) return LBM_EINVAL;   // Eq. 9 has no coexistence at this T and eps
+    const ld P = bisect(I, lo, hi);
+    ld g, l;
+    roots(P, g, l);
+    if (rho_g) *rho_g = (double)g;
+    if (rho_l) *rho_l = (double)l;
+    if (p0) *p0 = (double)P;
+    return LBM_OK;
+}

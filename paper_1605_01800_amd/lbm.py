@@ -110,6 +110,7 @@ _SIGS = {
     "lbm_set_variant": [ctypes.c_void_p, ctypes.c_int],
     "lbm_critical_point": [ctypes.c_double] * 3 + [ctypes.POINTER(ctypes.c_double)] * 3,
     "lbm_maxwell": [ctypes.c_double] * 4 + [ctypes.POINTER(ctypes.c_double)] * 3,
+    "lbm_mechanical_stability": [ctypes.c_double] * 6 + [ctypes.POINTER(ctypes.c_double)] * 3,
     "lbm_copy_kernel": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
 }
 
@@ -154,6 +155,15 @@ def maxwell(T, a=0.5, b=4.0, R=1.0):
     """(rho_g, rho_l, p0) of the Maxwell rule (Eq. 11) at temperature T."""
     out = [ctypes.c_double() for _ in range(3)]
     _check(lib().lbm_maxwell(a, b, R, T, *[ctypes.byref(o) for o in out]), "lbm_maxwell")
+    return tuple(o.value for o in out)
+
+
+def mechanical_stability(T, eps=1.86, a=0.5, b=4.0, R=1.0, G=-1.0):
+    """(rho_g, rho_l, p0) that the lattice model with Li's term settles to by
+    the mechanical-stability condition, Eq. 9; LbmError when it has none."""
+    out = [ctypes.c_double() for _ in range(3)]
+    _check(lib().lbm_mechanical_stability(a, b, R, T, G, eps, *[ctypes.byref(o) for o in out]),
+           "lbm_mechanical_stability")
     return tuple(o.value for o in out)
 
 

@@ -271,7 +271,9 @@ def coexistence_sweep(device, steps, T_over_Tc=(0.5, 0.6, 0.7, 0.8, 0.9), eps=(1
     """Flat liquid slabs (ny / 2 liquid rows in a periodic nx x ny box), one
     instance per (T, eps, tau_nu), each stepped on its own stream in chunks of
     1000 steps and averaged over the last quarter of the run: the coexisting
-    densities against the Maxwell rule.  An instance that turns non-finite is
+    densities against the Maxwell rule and against the mechanical-stability
+    condition of Eq. 9 for the instance's eps (None where it has no
+    solution).  An instance that turns non-finite is
     reported with the step count at which its latch was first seen (a
     multiple of 1000) and stops alone; the others go on."""
     from . import lbm as L
@@ -323,9 +325,14 @@ def coexistence_sweep(device, steps, T_over_Tc=(0.5, 0.6, 0.7, 0.8, 0.9), eps=(1
            "precision": precision, "averaged_over": "the records every %d steps in the last quarter" % chunk,
            "seconds": round(dt, 2), "cases": []}
     for i, c in enumerate(cases):
-        g, l, _ = L.maxwell(L.temperature(c["T_over_Tc"]))
+        T = L.temperature(c["T_over_Tc"])
+        g, l, _ = L.maxwell(T)
+        try:
+            g9, l9, _ = L.mechanical_stability(T, c["eps"])
+        except L.LbmError:
+            g9 = l9 = None
         e = dict(c)
-        e.update({"maxwell_rho_g": g, "maxwell_rho_l": l})
+        e.update({"maxwell_rho_g": g, "maxwell_rho_l": l, "eq9_rho_g": g9, "eq9_rho_l": l9})
         if i in bad or acc[i][2] == 0:
             e["nonfinite_step"] = bad.get(i)
         else:
@@ -333,6 +340,9 @@ def coexistence_sweep(device, steps, T_over_Tc=(0.5, 0.6, 0.7, 0.8, 0.9), eps=(1
             e["rho_g"] = acc[i][1] / acc[i][2]
             e["rho_l_rel_dev"] = (e["rho_l"] - l) / l
             e["rho_g_rel_dev"] = (e["rho_g"] - g) / g
+            if g9 is not None:
+                e["rho_l_rel_dev_eq9"] = (e["rho_l"] - l9) / l9
+                e["rho_g_rel_dev_eq9"] = (e["rho_g"] - g9) / g9
         out["cases"].append(e)
     for s in sims:
         s.close()

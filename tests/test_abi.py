@@ -55,6 +55,28 @@ def test_host_critical_point_and_maxwell_agree_with_oracle(coexistence_table):
         assert abs(g - mg) / mg < 1e-9 and abs(l - ml) / ml < 1e-11 and abs(p0 - mp0) / mp0 < 1e-9
 
 
+def test_host_mechanical_stability_agrees_with_oracle(coexistence_table):
+    """liblbm's Eq. 9 solver (composite Gauss-Legendre in ln rho, long double)
+    against the oracle's multiprecision solutions for eps = 0, 1, 1.86, 2 from
+    0.5 to 0.9 T_c, including where the condition has no solution (eps = 0
+    and 1 at low temperature) and must be reported as an error."""
+    L = pytest.importorskip("paper_1605_01800_amd.lbm")
+    for tr, row in coexistence_table.items():
+        for e in (0.0, 1.0, 1.86, 2.0):
+            want = row[("eq9", e)]
+            if want is None:
+                with pytest.raises(L.LbmError):
+                    L.mechanical_stability(row["T"], e)
+                continue
+            g, l, p0 = L.mechanical_stability(row["T"], e)
+            assert abs(g - want[0]) / want[0] < 1e-10, (tr, e)
+            assert abs(l - want[1]) / want[1] < 1e-10, (tr, e)
+    with pytest.raises(L.LbmError):
+        L.mechanical_stability(0.05, 1.0)            # above T_c
+    with pytest.raises(L.LbmError):
+        L.mechanical_stability(0.03, 1.0, G=1.0)     # repulsive G
+
+
 def test_invalid_parameters_are_rejected_without_a_device():
     L = pytest.importorskip("paper_1605_01800_amd.lbm")
     lib = L.lib()

@@ -45,11 +45,13 @@ def test_coexistence_against_eps_and_tau_nu(coexistence_table):
     # eps = 1 at 0.5 T_c: Eq. 9 has no solution and the run does not settle
     for tn in (0.6, 0.8):
         assert cases[(0.5, 1.0, tn)].get("nonfinite_step") is not None
+        assert cases[(0.5, 1.0, tn)]["eq9_rho_g"] is None
     # eps = 1 at 0.7 T_c: the gas density of Eq. 9, far below Maxwell's
     g9, l9, _ = coexist.mechanical_stability(coexist.temperature(0.7), 1.0)
     for tn in (0.6, 0.8):
         c = cases[(0.7, 1.0, tn)]
         assert abs(c["rho_g"] - g9) / g9 < 0.02, (c["rho_g"], g9)
+        assert abs(c["eq9_rho_g"] - g9) / g9 < 1e-10 and abs(c["rho_g_rel_dev_eq9"]) < 0.02
         assert c["rho_g"] < 0.3 * c["maxwell_rho_g"]
     # eps = 1.86 at 0.7 T_c: Maxwell within 2 % (gas) and 0.1 % (liquid)
     for tn in (0.6, 0.8):
