@@ -55,7 +55,11 @@ typedef enum {
 typedef enum {
     LBM_FP64 = 0,         /* populations and arithmetic in binary64 */
     LBM_FP32 = 1,         /* populations and arithmetic in binary32 */
-    LBM_FP32_MIXED = 2    /* binary32 populations; Eq. 15 and Eq. 13 in binary64 */
+    LBM_FP32_MIXED = 2    /* binary32 populations and arithmetic; Eq. 15 and Eq. 13
+                             in binary64 at sites whose density lies in the
+                             spinodal interval of Eq. 15 at T (lbm_spinodals),
+                             widened by a tenth of its width on each side (all
+                             sites in binary32 at or above T_c) */
 } lbm_precision;
 
 /* Parameters of one instance.  Section 3.1 fixes a = 0.5, R = 1, G = -1,
@@ -248,6 +252,13 @@ int lbm_step_timed(void *handle, int64_t n, float *ms);
 /* Critical point of Eq. 15: dp/drho = d2p/drho2 = 0.  Host only. */
 int lbm_critical_point(double a, double b, double R, double *T_c, double *rho_c,
                        double *p_c);
+
+/* Spinodal densities of Eq. 15 at temperature T < T_c: the gas-side local
+ * maximum and the liquid-side local minimum of p(rho) (dp/drho = 0), between
+ * which Eq. 15 is mechanically unstable.  LBM_EINVAL at or above T_c.  Host
+ * only. */
+int lbm_spinodals(double a, double b, double R, double T, double *rho_sg,
+                  double *rho_sl);
 
 /* Coexisting gas and liquid densities of Eq. 15 at temperature T < T_c by the
  * Maxwell rule (Eq. 11), solved as equal pressure and equal chemical

@@ -222,10 +222,25 @@ void fill_consts(Consts<T> &c, const InstDev &d)
 }
 
 // Refreshes the per-precision constant copies after a descriptor change.
+// Sites whose density lies in the spinodal interval of Eq. 15, widened by
+// MIX_PAD of its width on each side, evaluate Eqs. 15 and 13 in binary64 under
+// LBM_FP32_MIXED.
+constexpr double MIX_PAD = 0.1;
+
 void refresh_consts(InstDev &d)
 {
     fill_consts(d.cf, d);
     fill_consts(d.cd, d);
+    double sg, sl;
+    // p depends on R and T only through RT
+    if (lbm_spinodals(d.a, 4.0 * d.b4, 1.0, d.RT, &sg, &sl) == LBM_OK) {
+        const double pad = MIX_PAD * (sl - sg);
+        d.mix_lo = (float)(sg - pad - d.rho_ref);
+        d.mix_hi = (float)(sl + pad - d.rho_ref);
+    } else {
+        d.mix_lo = INFINITY;
+        d.mix_hi = -INFINITY;
+    }
 }
 
 void fill_desc(Instance *h)
@@ -1057,8 +1072,7 @@ int lbm_batch_autotune(void *batch, int reps, int *best_variant, float *ms_per_s
     // Three passes over the variants, each variant scored by its fastest
     // pass, so that a single disturbed measurement does not decide.
     constexpr int kPasses = 3;
-    float score[kNumVariants];
-    for (int v = 0; v < kNumVariants; ++v) score[v] = INFINITY;
+    std::vector<float> score(kNumVariants, INFINITY);
     int rc = LBM_OK;
     for (int pass = 0; pass < kPasses && rc == LBM_OK; ++pass) {
         for (int v = 0; v < kNumVariants && rc == LBM_OK; ++v) {

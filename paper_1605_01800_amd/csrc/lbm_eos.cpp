@@ -90,6 +90,20 @@ extern "C" int lbm_critical_point(double a, double b, double R, double *T_c, dou
     return LBM_OK;
 }
 
+extern "C" int lbm_spinodals(double a, double b, double R, double T, double *rho_sg, double *rho_sl)
+{
+    double Tc, rc;
+    if (lbm_critical_point(a, b, R, &Tc, &rc, nullptr) != LBM_OK) return LBM_EINVAL;
+    if (!(T > 0) || !(T < Tc)) return LBM_EINVAL;
+    const Cs cs{(ld)a, (ld)b / 4, (ld)R, (ld)T};
+    const ld pole = 4.0L / b;
+    // dp/drho = 0 on each side of the critical density: the local maximum of
+    // p on the gas side and the local minimum on the liquid side
+    if (rho_sg) *rho_sg = (double)bisect([&](ld r) { return cs.dp(r); }, 1e-12L, (ld)rc);
+    if (rho_sl) *rho_sl = (double)bisect([&](ld r) { return cs.dp(r); }, (ld)rc, pole * (1 - 1e-12L));
+    return LBM_OK;
+}
+
 extern "C" int lbm_maxwell(double a, double b, double R, double T, double *rho_g, double *rho_l,
                            double *p0)
 {

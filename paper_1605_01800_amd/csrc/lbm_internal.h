@@ -69,6 +69,9 @@ struct InstDev {
     // Populations are stored shifted by the rest equilibrium of rho_ref:
     // g_a = f_a - w_a rho_ref (rho_ref representable in the storage precision)
     double rho_ref;
+    // LBM_FP32_MIXED: Eqs. 15 and 13 in binary64 where mix_lo < rho - rho_ref
+    // < mix_hi (the widened spinodal interval; empty at or above T_c)
+    float mix_lo, mix_hi;
     double bx[LBM_MAX_BUBBLES], by[LBM_MAX_BUBBLES];
     Consts<float> cf;
     Consts<double> cd;

@@ -210,21 +210,22 @@ __device__ __forceinline__ const Consts<double> &consts<double>(const InstDev &d
 }
 
 // Pseudopotential, Eq. 13 with c = 1 and c_s^2 = 1/3, of a site whose shifted
-// populations sum to dm (rho = rho_ref + dm).  EOS64 forms rho and evaluates the
-// pressure and the root in binary64 whatever T is.
+// populations sum to dm (rho = rho_ref + dm).  With EOS64, a site whose density
+// lies in the instance's widened spinodal interval (mix_lo < dm < mix_hi) forms
+// rho and evaluates the pressure and the root in binary64; every other site
+// takes the working precision.  The choice is per lane.
 template <typename T, bool EOS64>
 __device__ __forceinline__ T pseudopotential(T dm, const InstDev &d)
 {
-    if (EOS64) {
+    if (EOS64 && dm > (T)d.mix_lo && dm < (T)d.mix_hi) {
         const double r = d.rho_ref + (double)dm;
         const double p = eos_pressure<double>(r, d.RT, d.a, d.b4);
         return (T)sqrt((p - r * (1.0 / 3.0)) * d.two_over_G);
-    } else {
-        const Consts<T> &c = consts<T>(d);
-        const T rho = c.rho_ref + dm;
-        const T p = eos_pressure<T>(rho, c.RT, c.a, c.b4);
-        return root((p - rho * T(1.0 / 3.0)) * c.two_over_G);
     }
+    const Consts<T> &c = consts<T>(d);
+    const T rho = c.rho_ref + dm;
+    const T p = eos_pressure<T>(rho, c.RT, c.a, c.b4);
+    return root((p - rho * T(1.0 / 3.0)) * c.two_over_G);
 }
 
 // Order-preserving map of a binary64 value onto an unsigned 64-bit key.

@@ -111,6 +111,7 @@ _SIGS = {
     "lbm_critical_point": [ctypes.c_double] * 3 + [ctypes.POINTER(ctypes.c_double)] * 3,
     "lbm_maxwell": [ctypes.c_double] * 4 + [ctypes.POINTER(ctypes.c_double)] * 3,
     "lbm_mechanical_stability": [ctypes.c_double] * 6 + [ctypes.POINTER(ctypes.c_double)] * 3,
+    "lbm_spinodals": [ctypes.c_double] * 4 + [ctypes.POINTER(ctypes.c_double)] * 2,
     "lbm_copy_kernel": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
 }
 
@@ -148,6 +149,13 @@ def critical_point(a=0.5, b=4.0, R=1.0):
     """(T_c, rho_c, p_c) of Eq. 15."""
     out = [ctypes.c_double() for _ in range(3)]
     _check(lib().lbm_critical_point(a, b, R, *[ctypes.byref(o) for o in out]), "lbm_critical_point")
+    return tuple(o.value for o in out)
+
+
+def spinodals(T, a=0.5, b=4.0, R=1.0):
+    """(rho_sg, rho_sl): where dp/drho of Eq. 15 vanishes at temperature T."""
+    out = [ctypes.c_double() for _ in range(2)]
+    _check(lib().lbm_spinodals(a, b, R, T, *[ctypes.byref(o) for o in out]), "lbm_spinodals")
     return tuple(o.value for o in out)
 
 

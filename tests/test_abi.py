@@ -55,6 +55,18 @@ def test_host_critical_point_and_maxwell_agree_with_oracle(coexistence_table):
         assert abs(g - mg) / mg < 1e-9 and abs(l - ml) / ml < 1e-11 and abs(p0 - mp0) / mp0 < 1e-9
 
 
+def test_host_spinodals_agree_with_oracle(coexistence_table):
+    """liblbm's spinodal densities (dp/drho = 0, long double) against the
+    oracle's multiprecision ones; none at or above T_c."""
+    L = pytest.importorskip("paper_1605_01800_amd.lbm")
+    for tr, row in coexistence_table.items():
+        sg, sl = L.spinodals(row["T"])
+        want_g, want_l = row["spinodal"]
+        assert abs(sg - want_g) / want_g < 1e-12 and abs(sl - want_l) / want_l < 1e-12, tr
+    with pytest.raises(L.LbmError):
+        L.spinodals(L.critical_point()[0])
+
+
 def test_host_mechanical_stability_agrees_with_oracle(coexistence_table):
     """liblbm's Eq. 9 solver (composite Gauss-Legendre in ln rho, long double)
     against the oracle's multiprecision solutions for eps = 0, 1, 1.86, 2 from

@@ -364,3 +364,41 @@ def test_empty_and_zero_step_calls_are_no_ops():
     empty.close()
     sim.close()
     other.close()
+
+
+@pytest.mark.parametrize("variant", ["fused-64x16", "fused2-128x16", "2pass-64x4"])
+def test_mixed_precision_uses_binary64_only_in_the_spinodal_interval(variant):
+    """LBM_FP32_MIXED evaluates Eqs. 15 and 13 in binary64 only at sites whose
+    density lies in the spinodal interval at T widened by a tenth of its width
+    on each side.  A state whose densities all lie outside it (gas and liquid
+    with a one-site jump, both perturbed by 1 %) steps bitwise like LBM_FP32;
+    a state with an Eq. 16 interface, whose densities cross the interval, does
+    not, and both stay within the single-step tolerance of the oracle."""
+    print("case mixed", variant, flush=True)
+    nx, ny = 96, 40
+    T = coexist.temperature(0.7)
+    rg, rl, _ = coexist.maxwell(T)
+    sg, sl = L.spinodals(T)
+    pad = 0.1 * (sl - sg)
+    rng = np.random.default_rng(5)
+    jump = np.where(np.arange(ny)[:, None] < ny // 2, rg, rl) * np.ones((1, nx))
+    jump = jump * (1 + 0.01 * (2 * rng.random((ny, nx)) - 1))
+    assert not np.any((jump > sg - pad) & (jump < sl + pad))
+    p64 = L.make_params(nx, ny, T=T, precision="fp64", tau_nu=0.6)
+    bubble, _, _ = _bubble_rho(oracle_params(p64), T, 12.5)
+    assert np.any((bubble > sg - pad) & (bubble < sl + pad))
+    for rho, same in ((jump, True), (bubble, False)):
+        out = {}
+        for prec in ("fp32", "fp32_mixed"):
+            sim = L.Sim(L.make_params(nx, ny, T=T, precision=prec, tau_nu=0.6))
+            sim.set_variant(_variant(variant))
+            sim.init_density(rho)
+            start = to_oracle(sim.populations())
+            sim.step(1)
+            got = sim.populations()
+            out[prec] = got.cpu().numpy()
+            want = start.copy()
+            assert ostep.step(oracle_params(sim.params), want, 1) == 0
+            assert rel_inf(to_oracle(got), want) < STEP_TOL[prec]
+            sim.close()
+        assert np.array_equal(out["fp32"], out["fp32_mixed"]) == same
