@@ -12,14 +12,21 @@ SRC = os.path.join(HERE, "lbm_oracle.c")
 LIB = os.path.join(HERE, "_lib", "liboracle.so")
 
 
+def compile_source(src, out, verbose=False, quiet=False):
+    """Compiles one C source into a shared library with the oracle's flags
+    (quiet: compiler messages are not shown)."""
+    cmd = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-ffp-contract=off",
+           "-fno-fast-math", "-fopenmp", "-Wall", "-Wextra", "-o", out, src, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True, capture_output=quiet)
+    return out
+
+
 def build(verbose=False):
     os.makedirs(os.path.dirname(LIB), exist_ok=True)
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-fopenmp", "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"]
-    if verbose:
-        print(" ".join(cmd))
-    subprocess.run(cmd, check=True)
+    compile_source(SRC, tmp, verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -4,6 +4,8 @@ Arrays are numpy float64 in the oracle's own layout: populations f[y, x, a]
 (shape (ny, nx, 9)), fields g[y, x] (shape (ny, nx)).
 """
 import ctypes
+import os
+
 import numpy as np
 
 from . import build as _build
@@ -23,9 +25,12 @@ class OracleParams(ctypes.Structure):
 
 
 def lib():
+    """The oracle library: the build of lbm_oracle.c, or the library that the
+    ORACLE_LIB environment variable names (the mutation tests load copies of
+    the oracle with a planted mistake this way)."""
     global _lib
     if _lib is None:
-        L = ctypes.CDLL(_build.ensure_built())
+        L = ctypes.CDLL(os.environ.get("ORACLE_LIB") or _build.ensure_built())
         P = ctypes.POINTER(OracleParams)
         dp = ctypes.POINTER(ctypes.c_double)
         L.oracle_eos_pressure.argtypes = [P, ctypes.c_double]

@@ -106,17 +106,27 @@ def test_li_term_properties():
         assert np.allclose(dh, 4 * d1, rtol=1e-8, atol=1e-16)
 
 
-def test_li_term_only_touches_energy_moments():
-    """The Li term enters only the e and zeta moments (rows 1 and 2 of Eq. 14)."""
+def test_li_term_through_the_collision_in_closed_form():
+    """Eq. 14's extra terms after (I - Lambda/2) of Eq. 3: since
+    (1 - s/2) / (tau - 1/2) = s for tau = 1/s, they add s_e Y to m*_e and
+    -s_zeta Y to m*_zeta, Y = 0.75 eps |F|^2 / psi^2, and nothing elsewhere.
+    Through the e row (-4, -1 x4, 2 x4) and the zeta row (4, -2 x4, 1 x4) of
+    M, whose squared norms are 36, f* changes by Y/36 times -4 s_e - 4 s_zeta
+    at rest, 2 s_zeta - s_e on the axes and 2 s_e - s_zeta on the diagonals.
+    With s_e != s_zeta, so that a rate taken from the other row fails (the
+    zeta part changes neither mass, momentum nor the second-order pressure
+    tensor, so the coexistence pins cannot see it)."""
     rng = np.random.default_rng(12)
-    rates = stepper.relaxation_rates(0.8)
-    M, _ = stepper.transform()
-    f, F, psi = _random_node(rng)
-    base = stepper.collide_node(_params(rates, 0.0), f, psi, F[0], F[1])
-    d = stepper.collide_node(_params(rates, 1.86), f, psi, F[0], F[1]) - base
-    dm = M @ d
-    assert np.allclose(np.delete(dm, [1, 2]), 0, atol=1e-15)
-    assert dm[1] > 0 and dm[2] < 0
+    s_e, s_z = 0.8, 1.3
+    rates = np.array([1.0, s_e, s_z, 1.0, 1.1, 1.0, 1.1, 1.0 / 0.8, 1.0 / 0.8])
+    for eps in (1.0, 1.86):
+        for _ in range(10):
+            f, F, psi = _random_node(rng)
+            base = stepper.collide_node(_params(rates, 0.0), f, psi, F[0], F[1])
+            d = stepper.collide_node(_params(rates, eps), f, psi, F[0], F[1]) - base
+            Y = 0.75 * eps * (F[0] ** 2 + F[1] ** 2) / psi ** 2
+            want = Y / 36.0 * np.array([-4 * s_e - 4 * s_z] + [2 * s_z - s_e] * 4 + [2 * s_e - s_z] * 4)
+            assert np.allclose(d, want, rtol=1e-9, atol=1e-16), (d, want)
 
 
 def test_each_moment_relaxes_at_its_own_rate():

@@ -1,0 +1,106 @@
+"""Mutation tests of the oracle's pins.
+
+Each case plants one plausible mistake in a copy of oracle/lbm_oracle.c (a
+dropped term, a wrong sign, coefficient, index or direction), compiles it with
+the oracle's flags, and runs the oracle's own tests (tests/test_oracle_*.py)
+against it in a separate process: a pin must fail for every mistake.  The
+oracle source itself is not changed; the copy is loaded through ORACLE_LIB.
+"""
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+from oracle import build as obuild
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# (name, text in lbm_oracle.c, the mistaken text); each text occurs once
+MUTANTS = [
+    ("eos_numerator_sign",          # Eq. 15, Z = (1 + eta + eta^2 - eta^3) / (1 - eta)^3
+     "double num = 1.0 + eta + eta * eta - eta * eta * eta;",
+     "double num = 1.0 + eta + eta * eta + eta * eta * eta;"),
+    ("psi_factor_two",              # Eq. 13 without its factor 2
+     "return sqrt(2.0 * (p - rho * cs2) / (P->G * c * c));",
+     "return sqrt((p - rho * cs2) / (P->G * c * c));"),
+    ("force_diagonal_weight",       # Eq. 7, w = 1/12 on the diagonals
+     "return (a <= 4) ? 1.0 / 3.0 : 1.0 / 12.0;",
+     "return (a <= 4) ? 1.0 / 3.0 : 1.0 / 6.0;"),
+    ("force_x_sign",                # Eq. 7, -G in front of the x component only
+     "Fx[i] = -P->G * psi[i] * sx;",
+     "Fx[i] = P->G * psi[i] * sx;"),
+    ("velocity_half_force",         # Eq. 6, half the force
+     "double vx = (jx + 0.5 * dt * Fx) / rho;",
+     "double vx = (jx + dt * Fx) / rho;"),
+    ("moment_matrix_entry",         # a q_x row with two diagonal entries swapped
+     "{ 0, -2,  0,  2,  0,  1, -1, -1,  1},   /* qx   */",
+     "{ 0, -2,  0,  2,  0,  1, -1,  1, -1},   /* qx   */"),
+    ("equilibrium_e_coefficient",   # Eq. 4, e row rho (-2 + 3 v^2)
+     "meq[1] = rho * (-2.0 + 3.0 * v2);",
+     "meq[1] = rho * (-2.0 + 2.0 * v2);"),
+    ("li_term_zeta_uses_tau_e",     # Eq. 14, tau_zeta in the zeta row
+     "- 0.75 * P->eps * F2 / (psi * psi * dt * (tau_z - 0.5));",
+     "- 0.75 * P->eps * F2 / (psi * psi * dt * (tau_e - 0.5));"),
+    ("li_term_dropped_from_zeta",   # Eq. 14 zeta row without Li's term
+     "S[2] = -6.0 * vF - 0.75 * P->eps * F2 / (psi * psi * dt * (tau_z - 0.5));",
+     "S[2] = -6.0 * vF;"),
+    ("source_without_half_rate",    # Eq. 3, (I - Lambda/2) S
+     "+ dt * (1.0 - 0.5 * P->s[k]) * S[k];",
+     "+ dt * (1.0 - P->s[k]) * S[k];"),
+    ("bounce_back_not_reversed",    # halfway bounce-back returns the opposite population
+     "fnew[((long)y * nx + x) * 9 + opposite(a)] = fstar[src];",
+     "fnew[((long)y * nx + x) * 9 + a] = fstar[src];"),
+    ("stream_x_backwards",          # Eq. 5, f_a moves to x + e_a
+     "int xd = ((x + EX[a]) % nx + nx) % nx;",
+     "int xd = ((x - EX[a]) % nx + nx) % nx;"),
+    ("wall_psi_zero",               # psi at solid sites: mirror, not 0
+     "if (y < 0) y = 0;\n        if (y > ny - 1) y = ny - 1;",
+     "if (y < 0 || y > ny - 1) return 0.0;"),
+    ("rest_weight",                 # f_a = w_a rho with w_0 = 4/9
+     "if (a == 0) return 4.0 / 9.0;",
+     "if (a == 0) return 1.0 / 3.0;"),
+]
+
+
+def _source():
+    with open(obuild.SRC) as fh:
+        return fh.read()
+
+
+def _run_pins(lib_path):
+    env = dict(os.environ, ORACLE_LIB=lib_path, OMP_NUM_THREADS="2")
+    tests = sorted(os.path.join(ROOT, "tests", f) for f in os.listdir(os.path.join(ROOT, "tests"))
+                   if f.startswith("test_oracle_") and f.endswith(".py") and "mutants" not in f)
+    cmd = [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu"] + tests
+    return subprocess.run(cmd, cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+
+
+def test_every_mutation_applies_once():
+    src = _source()
+    for name, old, new in MUTANTS:
+        assert src.count(old) == 1, name
+        assert old != new, name
+
+
+def test_every_planted_mistake_fails_a_pin(tmp_path):
+    """Every mutant fails a pin; a faithful copy, run through the same
+    harness alongside them, passes (so the failures are the mistakes')."""
+    src = _source()
+    libs = {}
+    for name, old, new in MUTANTS + [("faithful_copy", "", "")]:
+        c = tmp_path / (name + ".c")
+        c.write_text(src.replace(old, new) if old else src)
+        libs[name] = obuild.compile_source(str(c), str(tmp_path / (name + ".so")), quiet=True)
+    with ThreadPoolExecutor(max_workers=4) as pool:
+        runs = dict(zip(libs, pool.map(_run_pins, libs.values())))
+    control = runs.pop("faithful_copy")
+    assert control.returncode == 0, control.stdout[-2000:]
+    survivors = []
+    for name, r in runs.items():
+        tail = r.stdout.strip().splitlines()[-1] if r.stdout.strip() else r.stderr[-300:]
+        print(name, "->", tail)
+        # exit status 1 with a failed test: a pin caught it (2 and up would be
+        # a collection or usage error, which proves nothing)
+        if not (r.returncode == 1 and "failed" in tail):
+            survivors.append((name, r.returncode, tail))
+    assert not survivors, survivors
