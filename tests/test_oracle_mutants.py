@@ -59,6 +59,25 @@ MUTANTS = [
     ("rest_weight",                 # f_a = w_a rho with w_0 = 4/9
      "if (a == 0) return 4.0 / 9.0;",
      "if (a == 0) return 1.0 / 3.0;"),
+    ("source_pxx_factor",           # Eq. 14, 2 (vx Fx - vy Fy) in the pxx row
+     "S[7] = 2.0 * (vx * Fx - vy * Fy);",
+     "S[7] = (vx * Fx - vy * Fy);"),
+    ("equilibrium_qx_sign",         # Eq. 4, q_x^eq = -rho vx
+     "meq[4] = -rho * vx;",
+     "meq[4] = rho * vx;"),
+    ("wall_psi_periodic",           # psi at solid sites wrapped around instead of mirrored
+     "    if (P->walls) {\n        if (y < 0) y = 0;\n        if (y > ny - 1) y = ny - 1;\n    } else {\n"
+     "        y = ((y % ny) + ny) % ny;\n    }",
+     "    y = ((y % ny) + ny) % ny;"),
+    ("interface_width",             # Eq. 16, tanh(2 d / W)
+     "tanh(2.0 * d / W)",
+     "tanh(d / W)"),
+    ("noise_site_index",            # noise of site (x, y) drawn with index y nx + x
+     "oracle_uniform(seed, (uint64_t)i)",
+     "oracle_uniform(seed, (uint64_t)((long)x * ny + y))"),
+    ("macros_velocity_half_force",  # Eq. 6 in the reported velocity field
+     "vx[i] = (jx + 0.5 * Fx[i]) / rho[i];",
+     "vx[i] = jx / rho[i];"),
 ]
 
 

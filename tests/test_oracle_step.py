@@ -161,6 +161,31 @@ def test_splitmix64_reference_outputs():
         assert u == (w >> 11) * 2.0 ** -53
 
 
+def _splitmix64(s):
+    """One SplitMix64 output from state s (Steele, Lea and Flood, 2014),
+    written here from its published definition, apart from the oracle's."""
+    m = 2 ** 64 - 1
+    z = (s + 0x9E3779B97F4A7C15) & m
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+    return z ^ (z >> 31)
+
+
+def test_noise_of_each_site_uses_its_row_major_index():
+    """The noise reading: site (x, y) is scaled by 1 + amp (2u - 1), u the
+    SplitMix64 deviate of seed XOR (y nx + x) taken to 53 bits.  On a
+    non-square grid, so a transposed index fails."""
+    nx, ny, amp, seed = 23, 17, 1e-3, 0x5EED1234
+    P = stepper.make_params(nx, ny, T07)
+    kw = dict(bubbles=[(11.0, 8.0, 5.0)], rho_l=RL07, rho_g=RG07, W=5.0)
+    base = stepper.init_density(P, **kw)
+    noisy = stepper.init_density(P, noise_amp=amp, seed=seed, **kw)
+    for y in range(ny):
+        for x in range(nx):
+            u = (_splitmix64(seed ^ (y * nx + x)) >> 11) * 2.0 ** -53
+            assert noisy[y, x] == base[y, x] * (1.0 + amp * (2.0 * u - 1.0)), (x, y)
+
+
 def test_noise_is_bounded_and_seeded():
     P = stepper.make_params(50, 40, T07)
     base = stepper.init_density(P, bubbles=[(25, 20, 8)], rho_l=RL07, rho_g=RG07, W=5.0)
