@@ -95,7 +95,7 @@ def test_variants_are_bitwise_identical(prec):
             assert torch.equal(o, ref), name
 
 
-def test_config1_fp64_matches_oracle_over_10000_steps():
+def test_periodic_64x64_fp64_matches_oracle_over_10000_steps():
     """64 x 64 periodic, FP64, T = 0.7 T_c, bubble R = 16 at the centre, W = 2,
     tau_nu = 0.8 (nu = 0.1); rho field, mass and radius every 500 steps."""
     T = coexist.temperature(0.7)
@@ -124,7 +124,7 @@ def test_config1_fp64_matches_oracle_over_10000_steps():
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp32_mixed"])
-def test_config1_fp32_within_1e4(prec):
+def test_periodic_64x64_fp32_within_1e4(prec):
     T = coexist.temperature(0.7)
     rg, rl, _ = coexist.maxwell(T)
     p = L.make_params(64, 64, T=T, precision=prec, tau_nu=0.8)
