@@ -25,7 +25,7 @@ pytestmark = pytest.mark.gpu
 L = pytest.importorskip("paper_1605_01800_amd.lbm")
 from paper_1605_01800_amd import inputs, studies  # noqa: E402
 
-STEP_TOL = {"fp64": 1e-14, "fp32": 2e-6}
+STEP_TOL = {"fp64": 1e-14, "fp32": 2e-6, "fp32_mixed": 2e-6}
 
 
 def _batch(sims, precision, variant):
@@ -73,7 +73,7 @@ def _windows(nx, ny, bub, h=32, w=40):
 
 
 @pytest.mark.parametrize("prec,variant", [("fp32", "fused2-128x16"), ("fp32", "fused-64x16"),
-                                          ("fp64", "fused-64x16")])
+                                          ("fp64", "fused-64x16"), ("fp32_mixed", "fused2-128x16")])
 def test_collapse_large_full_size_sampled_windows(prec, variant):
     print("case large", prec, variant, flush=True)
     nx, ny = 8192, 4096
