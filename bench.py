@@ -125,6 +125,29 @@ def calibrate_copy(mib):
                       "GB_s": 2 * n / (ms * 1e-3) / 1e9}), flush=True)
 
 
+def copy_rate(L, nbytes, stream, reps=50):
+    """GB/s of the library's plain copy kernel moving nbytes into another nbytes
+    (so 2 nbytes of traffic per launch), launched back to back on `stream`:
+    what the memory system delivers for a launch's worth of bytes, launch cost
+    included."""
+    import torch
+    n = max(16, (int(nbytes) + 15) // 16 * 16)
+    with torch.cuda.stream(stream):
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+    for _ in range(5):
+        L.copy_kernel(dst, src, n, stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        L.copy_kernel(dst, src, n, stream)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * n / (ms * 1e-3) / 1e9
+
+
 def collapse_large_sims(L, precision, device):
     from paper_1605_01800_amd import inputs
     nx, ny = 8192, 4096
@@ -409,6 +432,7 @@ def main():
                                                                      dominant[2]), file=sys.stderr, flush=True)
 
     traffic = measured_traffic(args.workload, vname)
+    copy_gbs = copy_rate(L, dominant[2] * sites // 2, batch.stream)
     out = {
         "metric": "aggregate MLUPS + %HBM roofline (FP32 batched vs FP64 plain); p50/p99 latency",
         "value": round(mlups, 1),
@@ -437,6 +461,11 @@ def main():
             "launch_ms": dominant[1],
             "algorithmic_bytes_per_launch": dominant[2] * sites,
             "traffic_over_algorithmic": None if traffic is None else round(traffic / (dominant[2] * sites), 4),
+            # a plain copy of the launch's algorithmic bytes (half read, half
+            # written), back to back on the same stream: what this traffic can
+            # reach on this part, launch cost included
+            "copy_same_bytes_GB_s": round(copy_gbs, 1),
+            "frac_of_copy": round(achieved / copy_gbs, 4),
         },
         "kernels": kernels,
     }
