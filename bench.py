@@ -3,15 +3,19 @@ MI355X.
 
 Default workload: the Laplace-law and coexistence sweep (24 instances of a
 256 x 256 periodic grid: discs of radius 20..60 at T/Tc 0.6..0.9 plus one liquid
-slab per temperature), binary32, stepped as one batch over the tiles of all 24
-instances with the tile variant the autotuner picks (normally the fused
-single-pass kernel: one launch per step), replayed from captured HIP graphs.  A
-"step" advances all 24 instances by one timestep.
+slab per temperature), binary32, with the tile variant the autotuner picks
+(normally the fused single-pass kernel: one launch per step), replayed from
+captured HIP graphs.  A "step" advances all 24 instances by one timestep.  The
+steps are timed twice: as one batch over the tiles of all 24 instances on one
+stream (one launch per step over every site), then spread over four batches on
+four streams whose launches run concurrently (`value`).
 
-Prints one JSON line: aggregate MLUPS (million lattice-site updates per second),
-the roofline of the dominant kernel (algorithmic HBM bytes of the stated
-per-site model over its timed duration, and the measured HBM traffic when a
-counter record for the current kernel source exists), the oracle's CPU rate on
+Prints one JSON line: aggregate MLUPS (million lattice-site updates per second)
+of the concurrent run, the roofline of the dominant kernel from the one-stream
+run (algorithmic HBM bytes of the stated per-site model over its timed launch
+duration, and the measured HBM traffic when a counter record for the current
+kernel source exists) with the concurrent run's figures beside it, the
+oracle's CPU rate on
 a bounded sample, the plain per-instance binary64 rate (one instance at a time,
 direct launches, no graph, no batch) and the served-batch latencies.
 
@@ -49,12 +53,45 @@ def timing_part(steps, warmup):
     return max(small) if small else max(divisors)
 
 
-def measured_traffic(workload, variant_name):
-    """HBM bytes per launch of the dominant kernel from the rocprofv3 FETCH_SIZE
-    and WRITE_SIZE counters recorded in profiles/traffic.json (each scaled by
-    what the counter reads for a copy kernel of known size), or None when no
-    record matches this workload and tile variant or the kernel source has
-    changed since the counters were taken."""
+def timed_region(torch, runner, main, group, steps, warmup):
+    """Times `steps` steps of `runner` (a Batch, or a BatchGroup given also as
+    `group`) with HIP events on stream `main`; returns (ms, median ms per step
+    of the parts, parts).  The timed steps run as equal parts with events
+    between them (the whole region gives the time; the parts give a median),
+    the warm-up in pieces of the same size so that their graphs are captured
+    beforehand.  With several streams every part starts after the previous
+    one has ended on all of them (fork from and join into `main`)."""
+    part = timing_part(steps, warmup)
+    done = 0
+    while done < warmup:
+        n = min(part, warmup - done)
+        runner.step(n)
+        done += n
+    runner.sync()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps // part + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(main)
+    for i in range(1, len(ev)):
+        if group is not None:
+            group.fork(ev[i - 1])
+        runner.step(part)
+        if group is not None:
+            group.join(main)
+        ev[i].record(main)
+    ev[-1].synchronize()
+    ms = ev[0].elapsed_time(ev[-1])
+    part_ms = sorted(ev[i - 1].elapsed_time(ev[i]) / part for i in range(1, len(ev)))
+    torch.cuda.synchronize()
+    return ms, part_ms[len(part_ms) // 2], len(part_ms)
+
+
+def measured_traffic(workload, variant_name, launches_per_step):
+    """HBM bytes of one step of the dominant kernel (all its launches in the
+    step) from the rocprofv3 FETCH_SIZE and WRITE_SIZE counters recorded in
+    profiles/traffic.json (each scaled by what the counter reads for a copy
+    kernel of known size), or None when no record matches this workload, tile
+    variant and number of launches per step, or the kernel source has changed
+    since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     src = os.path.join(ROOT, "paper_1605_01800_amd", "csrc", "lbm_kernels.hip")
@@ -65,22 +102,29 @@ def measured_traffic(workload, variant_name):
             sha = hashlib.sha256(fh.read()).hexdigest()
     except (OSError, ValueError):
         return None
-    e = rec.get("entries", {}).get(workload)
-    if rec.get("kernels_source_sha256") != sha or not e or e.get("variant") != variant_name:
+    if not isinstance(rec, dict) or rec.get("kernels_source_sha256") != sha:
         return None
-    return e["bytes_per_launch"]
+    found = rec.get("entries", {}).get(workload, [])
+    for e in (found if isinstance(found, list) else [found]):
+        if (isinstance(e, dict) and e.get("variant") == variant_name
+                and e.get("launches_per_step", 1) == launches_per_step and "bytes_per_step" in e):
+            return e["bytes_per_step"]
+    return None
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=1280)
+    ap.add_argument("--warmup", type=int, default=256)
     ap.add_argument("--workload", default="laplace_sweep",
                     choices=["laplace_sweep", "collapse_large", "collapse_shard", "precision_large",
                              "collapse_horizon",
                              "laplace_physics", "coexistence_sweep", "critical_nucleus", "paper_collapse",
                              "single_small"])
+    ap.add_argument("--streams", type=int, default=0,
+                    help="batches (one stream each) the instances are spread over; 0: 4 for "
+                         "workloads of several instances, 1 otherwise")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-plain", action="store_true")
     ap.add_argument("--variant", type=int, default=-1, help="tile variant; -1 autotunes")
@@ -373,52 +417,68 @@ def main():
     else:
         variant, _ = batch.autotune(reps=20)
     workload["tile"] = L.variant_names()[variant]
-    print("# workload %s sites %d variant %s" % (args.workload, sites, workload["tile"]),
-          file=sys.stderr, flush=True)
-
-    # The timed steps run as five equal parts with events between them (the
-    # whole region gives `value`; the parts give a median), the warm-up in
-    # pieces of the same size so that their graphs are captured beforehand.
-    part = timing_part(args.steps, args.warmup)
-    done = 0
-    while done < args.warmup:
-        n = min(part, args.warmup - done)
-        batch.step(n)
-        done += n
-    batch.sync()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps // part + 1)]
-    torch.cuda.synchronize()
-    ev[0].record(batch.stream)
-    for i in range(1, len(ev)):
-        batch.step(part)
-        ev[i].record(batch.stream)
-    ev[-1].synchronize()
-    ms = ev[0].elapsed_time(ev[-1])
-    part_ms = sorted(ev[i - 1].elapsed_time(ev[i]) / part for i in range(1, len(ev)))
-    median_ms = part_ms[len(part_ms) // 2]
-    torch.cuda.synchronize()
-    for s in sims:
-        s.sync()                          # raises if a non-finite value was latched
-    mlups = sites * args.steps / (ms * 1e-3) / 1e6
-    print("# timed %d steps: %.3f ms/step, %.0f MLUPS" % (args.steps, ms / args.steps, mlups),
-          file=sys.stderr, flush=True)
-
-    # Dominant kernel.  Fused variants launch one kernel per step, so its average
-    # launch duration is the timed region over the step count (an upper bound:
-    # it includes the gaps between launches and one end-of-chunk kernel per 256
-    # steps).  Two-pass variants time each launch with its own event pair on the
-    # batch's stream.
+    # Independent instances can also be spread over several batches, one
+    # stream each, whose kernels then run concurrently (one batch's start-up,
+    # tail and kernel boundary overlap another's work); a step is then one
+    # launch per batch.
+    n_streams = args.streams if args.streams > 0 else (4 if len(sims) >= 4 else 1)
+    n_streams = min(n_streams, len(sims))
     vname = L.variant_names()[variant]
     fused = not vname.startswith("2pass")
+    if not fused:
+        n_streams = 1                     # their launches are timed one batch at a time
+    workload["streams"] = n_streams
+    print("# workload %s sites %d variant %s streams %d" % (args.workload, sites, vname, n_streams),
+          file=sys.stderr, flush=True)
+
+    # First the whole batch on one stream: one launch per step over every
+    # site, timed as a region with HIP events on that stream.  This gives the
+    # dominant kernel's launch duration for the roofline, and matches a
+    # kernel trace launch for launch (a profiler serialises concurrent
+    # streams, so their launches cannot be checked against a trace).
+    ms1, median1, nparts1 = timed_region(torch, batch, batch.stream, None, args.steps, args.warmup)
+    for s in sims:
+        s.sync()                          # raises if a non-finite value was latched
+    print("# one stream, %d steps: %.4f ms/step, %.0f MLUPS" % (args.steps, ms1 / args.steps,
+                                                                sites * args.steps / (ms1 * 1e-3) / 1e6),
+          file=sys.stderr, flush=True)
+
+    # Then the job as it runs best: with several streams, the instances in
+    # n_streams batches stepped concurrently.  `value` is this region.
+    group = None
+    if n_streams > 1:
+        for s in sims:
+            batch.detach(s)
+        group = L.BatchGroup(sims, precision=precision, n_batches=n_streams, device=device)
+        group.set_variant(variant)
+        ms, median_ms, nparts = timed_region(torch, group, group.streams[0], group, args.steps, args.warmup)
+    else:
+        ms, median_ms, nparts = ms1, median1, nparts1
+    for s in sims:
+        s.sync()
+    mlups = sites * args.steps / (ms * 1e-3) / 1e6
+    print("# timed %d steps on %d stream(s): %.4f ms/step, %.0f MLUPS" % (args.steps, n_streams,
+                                                                        ms / args.steps, mlups),
+          file=sys.stderr, flush=True)
+
+    # Dominant kernel.  Fused variants launch one kernel per step, so on one
+    # stream a launch lasts the timed region over the step count (an upper
+    # bound: it includes the gaps between launches and one end-of-chunk
+    # kernel per 256 steps) and moves the bytes of all sites.  Two-pass
+    # variants time each launch with its own event pair on the batch's stream.
     nk = min(args.steps, 100)
+    if group is not None:
+        group.close()
+        for s in sims:
+            batch.attach(s)
     ms_psi, ms_col = batch.step_timed(nk)
     if fused:
-        t_dom = ms / args.steps
+        t_dom = ms1 / args.steps
         kname = {"fused2": "fused2_kernel", "fused": "fused_kernel"}[vname.split("-")[0]]
         dominant = (kname, t_dom, BYTES_FUSED[es])
         kernels = {kname: {"ms_region_avg": t_dom, "ms_event_pair_avg": ms_col / nk,
-                                    "bytes_per_site": BYTES_FUSED[es],
-                                    "GB_s": round(BYTES_FUSED[es] * sites / (t_dom * 1e-3) / 1e9, 1)}}
+                           "bytes_per_site": BYTES_FUSED[es],
+                           "GB_s": round(BYTES_FUSED[es] * sites / (t_dom * 1e-3) / 1e9, 1)}}
     else:
         t_psi, t_col = ms_psi / nk, ms_col / nk
         dominant = ("collide_stream_kernel", t_col, BYTES_COLLIDE[es]) if t_col >= t_psi else \
@@ -431,7 +491,7 @@ def main():
     print("# dominant %s %.4f ms/launch, %.0f GB/s of %d B/site" % (dominant[0], dominant[1], achieved,
                                                                      dominant[2]), file=sys.stderr, flush=True)
 
-    traffic = measured_traffic(args.workload, vname)
+    traffic = measured_traffic(args.workload, vname, 1)
     copy_gbs = copy_rate(L, dominant[2] * sites // 2, batch.stream)
     out = {
         "metric": "aggregate MLUPS + %HBM roofline (FP32 batched vs FP64 plain); p50/p99 latency",
@@ -442,7 +502,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": ms / args.steps,
         "ms_per_step_median_of_parts": median_ms,
-        "timed_parts": len(part_ms),
+        "timed_parts": nparts,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -456,19 +516,31 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "launch_ms": dominant[1],
             "traffic": traffic,
             "bytes_per_site": dominant[2],
-            "launch_ms": dominant[1],
             "algorithmic_bytes_per_launch": dominant[2] * sites,
             "traffic_over_algorithmic": None if traffic is None else round(traffic / (dominant[2] * sites), 4),
-            # a plain copy of the launch's algorithmic bytes (half read, half
-            # written), back to back on the same stream: what this traffic can
+            # a plain copy of the step's algorithmic bytes (half read, half
+            # written), back to back on one stream: what this traffic can
             # reach on this part, launch cost included
             "copy_same_bytes_GB_s": round(copy_gbs, 1),
             "frac_of_copy": round(achieved / copy_gbs, 4),
         },
         "kernels": kernels,
     }
+    if group is not None:
+        # the step's launches on all streams, each over its batch's share of
+        # the sites: the step's algorithmic bytes over the step's time, and
+        # the step's measured bytes (launches of a quarter of the grid)
+        step_ms = ms / args.steps
+        c_traffic = measured_traffic(args.workload, vname, n_streams)
+        c_achieved = dominant[2] * sites / (step_ms * 1e-3) / 1e9
+        out["roofline"]["concurrent_streams"] = {
+            "streams": n_streams, "launches_per_step": n_streams, "step_ms": step_ms,
+            "achieved": round(c_achieved, 1), "frac": round(c_achieved / HBM_PEAK_GBS, 4),
+            "frac_of_copy": round(c_achieved / copy_gbs, 4), "traffic": c_traffic,
+            "traffic_over_algorithmic": None if c_traffic is None else round(c_traffic / (dominant[2] * sites), 4)}
     batch.close()
     for s in sims:
         s.close()

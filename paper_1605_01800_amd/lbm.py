@@ -471,6 +471,65 @@ class Batch:
             pass
 
 
+class BatchGroup:
+    """Independent instances spread round-robin over several batches, each on
+    its own stream (default priority), stepped together: the batches' kernels
+    run concurrently, so one batch's start-up and tail, and the gap at its
+    kernel boundaries, overlap another's work.  Results are bitwise those of
+    one batch (the same kernels on the same tiles)."""
+
+    def __init__(self, sims, precision="fp32", n_batches=4, device="cuda"):
+        n = max(1, min(int(n_batches), len(sims)))
+        groups = [list(sims[i::n]) for i in range(n)]
+        self.batches = []
+        for g in groups:
+            b = Batch(precision=precision, max_instances=len(g),
+                      max_tiles=sum(tile_count(s.params) for s in g), device=device)
+            for s in g:
+                b.attach(s)
+            self.batches.append(b)
+
+    @property
+    def streams(self):
+        return [b.stream for b in self.batches]
+
+    def set_variant(self, v):
+        for b in self.batches:
+            b.set_variant(v)
+
+    def step(self, n=1):
+        for b in self.batches:
+            b.step(n)
+
+    def fork(self, event):
+        """Makes every batch's stream wait for `event` (recorded by the caller)."""
+        for st in self.streams:
+            st.wait_event(event)
+
+    def join(self, stream):
+        """Makes `stream` wait for all work enqueued so far on every batch."""
+        for st in self.streams:
+            if st != stream:
+                e = torch.cuda.Event()
+                e.record(st)
+                stream.wait_event(e)
+
+    def sync(self):
+        for b in self.batches:
+            b.sync()
+
+    def close(self):
+        for b in self.batches:
+            b.close()
+        self.batches = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def copy_kernel(dst, src, nbytes, stream=None):
     """Plain device copy of nbytes (multiple of 16) with liblbm's copy kernel."""
     s = stream.cuda_stream if stream is not None else torch.cuda.current_stream().cuda_stream

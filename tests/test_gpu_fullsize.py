@@ -243,3 +243,25 @@ def test_collapse_full_horizon_binary32_against_binary64():
     assert ew < 1e-4 and h32[-1]["wall_p_step"] == h64[-1]["wall_p_step"]
     assert e5 < 1e-4
     assert erms < 1e-4 and emax < 2e-3
+
+
+def test_batch_group_equals_one_batch_bitwise():
+    """The sweep's 24 instances spread over four batches on four streams, as
+    bench.py times them, step bitwise like the same instances in one batch."""
+    print("case batch group", flush=True)
+    out = []
+    for n_batches in (1, 4):
+        sims = studies.laplace_sweep_sims(L, "fp32", "cuda:0")
+        if n_batches == 1:
+            runner = _batch(sims, "fp32", "fused-64x16")
+        else:
+            runner = L.BatchGroup(sims, precision="fp32", n_batches=n_batches)
+            runner.set_variant(L.variant_names().index("fused-64x16"))
+        runner.step(300)
+        runner.sync()
+        out.append([s.populations().cpu().numpy() for s in sims])
+        runner.close()
+        for s in sims:
+            s.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
