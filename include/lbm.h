@@ -226,6 +226,15 @@ void lbm_batch_destroy(void *batch);
 /* Number of tile-shape variants and a short name for each. */
 int lbm_variant_count(void);
 const char *lbm_variant_name(int variant);
+/* Blocks (tiles) of a fused variant's kernel that the current device holds at
+ * once in the given precision mode, from the runtime's occupancy query, made
+ * once per process at the first lbm_create or lbm_batch_create (0 before that,
+ * and for the two-pass variants).  A fused launch whose tiles fit walks every
+ * other band of tiles downwards, so that vertically neighbouring tiles, which
+ * then run side by side, read their shared rows at the same time; a larger
+ * launch walks every tile upwards.  Results do not depend on the walk.
+ * LBM_EINVAL for an unknown variant or precision or a null blocks. */
+int lbm_resident_blocks(int precision, int variant, int *blocks);
 /* Selects the tile-shape variant a handle or a batch launches.  Results are
  * bitwise the same for every variant except the paired ones ("fused2-*"),
  * whose compiler contracts a few products differently (last-bit differences,

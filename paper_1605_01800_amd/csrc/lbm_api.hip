@@ -561,6 +561,7 @@ int lbm_create(const lbm_params *params, void *d_workspace, size_t ws_bytes, voi
     h->d_desc = (InstDev *)(h->ws + L.desc);
     h->d_tiles = (Tile *)(h->ws + L.tiles);
     fill_desc(h);
+    prime_residency();
     if (h->stager.init(sizeof(InstDev)) != LBM_OK) {
         h->stager.release();
         delete h;
@@ -910,6 +911,15 @@ const char *lbm_variant_name(int variant)
     return kVariants[variant].name;
 }
 
+int lbm_resident_blocks(int precision, int variant, int *blocks)
+{
+    if (!blocks || variant < 0 || variant >= kNumVariants || precision < LBM_FP64 ||
+        precision > LBM_FP32_MIXED)
+        return LBM_EINVAL;
+    *blocks = resident_blocks(precision, variant);
+    return LBM_OK;
+}
+
 int lbm_set_variant(void *handle, int variant)
 {
     Instance *h = (Instance *)handle;
@@ -948,6 +958,7 @@ int lbm_batch_create(int precision, int max_instances, int64_t max_tiles, void *
     b->d_descs = (InstDev *)d_workspace;
     b->d_tiles = (Tile *)((char *)d_workspace + round_up(sizeof(InstDev) * (size_t)max_instances, ALIGN));
     b->d_status = (int *)((char *)b->d_tiles + round_up(sizeof(Tile) * (size_t)max_tiles, ALIGN));
+    prime_residency();
     if (hipMemsetAsync(b->d_status, 0, sizeof(int) * (size_t)max_instances, b->stream) != hipSuccess) {
         delete b;
         return LBM_EHIP;

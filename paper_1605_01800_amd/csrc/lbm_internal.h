@@ -108,6 +108,14 @@ inline int tile_cols(int variant) { return kVariants[variant].fused == 2 ? 2 * T
 
 inline bool variant_fits(int variant, int nx) { return kVariants[variant].fused != 2 || nx % 2 == 0; }
 
+// Records, once per process, how many blocks of each fused kernel the
+// current device holds at once (the fused kernels change their walk order
+// when a whole grid fits).  Called where handles and batches are created,
+// never under graph capture.
+void prime_residency();
+// Those blocks for one precision mode and variant (0: not known, or two-pass).
+int resident_blocks(int prec, int variant);
+
 // Kernels, launched on a stream.  prec is an lbm_precision.
 hipError_t launch_psi_pass(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles,
                            int ntiles, int s, hipStream_t st);

@@ -20,6 +20,8 @@
 // contiguous run of tiles, which keeps halo re-reads in that XCD's L2.
 #include <math.h>
 
+#include <mutex>
+
 #include "lbm_internal.h"
 
 namespace lbm {
@@ -586,7 +588,8 @@ __device__ __forceinline__ int memory_row(int l, int ny, int walls)
 
 template <typename T, bool EOS64, int H>
 __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict__ insts,
-                                                      const Tile *__restrict__ tiles, int ntiles, int s)
+                                                      const Tile *__restrict__ tiles, int ntiles, int s,
+                                                      int alternate)
 {
     constexpr int RING = 16;
     constexpr int LW = TILE_X + 2;
@@ -633,16 +636,32 @@ __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict_
 #pragma unroll
     for (int a = 0; a < 9; ++a) fq[a] = fn[a] = fa[a] = fb[a] = T(0);
 
+    // The tile's rows y0 - 1 .. l_last are walked upwards.  When the whole
+    // grid is resident at once (`alternate`), every other band of tiles (odd
+    // y0 / H) walks downwards instead: two vertically neighbouring tiles,
+    // which then run side by side, reach the rows around their common edge
+    // at about the same time (both at the start or both at the end of their
+    // walks), so the second reader of those rows finds them in L2, where
+    // upward walks would read them a whole walk apart.  A grid that runs in
+    // successive waves of blocks keeps the upward walk: there a band's
+    // blocks start about when the band below them finishes, which lines up
+    // their common rows already.
+    const int l_first = tl.y0 - 1;
+    const int l_last = min(tl.y0 + H, ny);
+    const bool down = alternate && ((tl.y0 / H) & 1) != 0;
+    const int dir = down ? -1 : 1;
+    const int l_start = down ? l_last : l_first;
+    auto row_of = [&](int k) { return l_start + dir * (ROW_GROUPS * k + w); };
+
     // Every load is issued unconditionally, so that the loads in flight are
     // the same on every path and the compiler's wait counts stay exact (a
     // load under a branch makes it wait for all outstanding loads, the
-    // prefetch included).  Rows past the strip's last needed row are clamped
-    // to that row (already being loaded by another wavefront of the block, so
-    // served from cache) and never used.
-    const int l_last = min(tl.y0 + H, ny);
-    auto row_loaded = [&](int k, int l) { return k < NLOAD && l <= l_last; };
+    // prefetch included).  Rows past the walk's last row are clamped to that
+    // row (already being loaded by another wavefront of the block, so served
+    // from cache) and never used.
+    auto row_loaded = [&](int k, int l) { return k < NLOAD && l >= l_first && l <= l_last; };
     auto load_row = [&](int k, T v[9], T &h) {
-        const int l = min(tl.y0 - 1 + ROW_GROUPS * k + w, l_last);
+        const int l = min(max(row_of(k), l_first), l_last);
         const gptr<const char> rb = f + (unsigned long long)memory_row(l, ny, walls) * RB;
         h = ld_lane<T>(rb, hoff);
 #pragma unroll
@@ -651,13 +670,13 @@ __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict_
     load_row(0, fn, hn);
 
     // Iteration k: loads row k + 1 (when `next`), forms psi of row k and
-    // collides row k - 2.
+    // collides row k - 2 (rows counted along the walk).
     auto iteration = [&](int k, bool next) __attribute__((always_inline)) {
-        const int l = tl.y0 - 1 + ROW_GROUPS * k + w;         // row handled now
+        const int l = row_of(k);                              // row handled now
         const bool have = row_loaded(k, l);
         if (next) load_row(k + 1, fq, hq);                    // in flight until the next iteration
 
-        T *row = ring + ((l + 2 * RING) % RING) * LW;
+        T *row = ring + (l & (RING - 1)) * LW;
         if (have) {
             const T dm_h = halo_density<T>(hn);
             if (hroot) {
@@ -676,12 +695,14 @@ __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict_
             if (track && (l == 0 || l == ny - 1) && l >= tl.y0 && l < y_end && x < nx)
                 wmax = fmax(wmax, eos_pressure<double>(d.rho_ref + (double)dm, d.RT, d.a, d.b4));
         }
-        // collide the row handled two iterations ago
-        const int c = l - 2 * ROW_GROUPS;
+        // collide the row handled two iterations ago; its psi neighbours
+        // were handled before the last barrier, and this iteration's psi
+        // rows lie 4 to 12 rows from them, so they never share a ring slot
+        const int c = l - dir * 2 * ROW_GROUPS;
         if (k >= 2 && c >= tl.y0 && c < y_end && x < nx) {
-            const T *rS = ring + ((c - 1 + 2 * RING) % RING) * LW;
-            const T *rC = ring + ((c + 2 * RING) % RING) * LW;
-            const T *rN = ring + ((c + 1 + 2 * RING) % RING) * LW;
+            const T *rS = ring + ((c - 1) & (RING - 1)) * LW;
+            const T *rC = ring + (c & (RING - 1)) * LW;
+            const T *rN = ring + ((c + 1) & (RING - 1)) * LW;
             T pc, Fx, Fy;
             interaction_force<T>(rS, rC, rN, lane + 1, mG, pc, Fx, Fy);
             collide_site<T>(fb, pc, Fx, Fy, R);
@@ -798,7 +819,8 @@ __device__ __forceinline__ void store_pair(gptr<char> row, int shift, T v0, T v1
 
 template <typename T, bool EOS64, int H>
 __global__ __launch_bounds__(BLOCK) void fused2_kernel(const InstDev *__restrict__ insts,
-                                                       const Tile *__restrict__ tiles, int ntiles, int s)
+                                                       const Tile *__restrict__ tiles, int ntiles, int s,
+                                                       int alternate)
 {
     using V = typename Pair<T>::type;
     constexpr int RING = 16;
@@ -862,9 +884,17 @@ __global__ __launch_bounds__(BLOCK) void fused2_kernel(const InstDev *__restrict
     // bandwidth at four wavefronts per SIMD, and the unconditional form
     // (more load instructions, the next row's loads overlapping the stores)
     // measured 3 % slower on the 8192 x 4096 grid.
-    auto row_loaded = [&](int k, int l) { return k < NLOAD && l <= tl.y0 + H && l <= ny; };
+    // Rows y0 - 1 .. l_last, walked upwards or, with `alternate`, downwards
+    // in every other band of tiles, as in fused_kernel.
+    const int l_first = tl.y0 - 1;
+    const int l_last = min(tl.y0 + H, ny);
+    const bool down = alternate && ((tl.y0 / H) & 1) != 0;
+    const int dir = down ? -1 : 1;
+    const int l_start = down ? l_last : l_first;
+    auto row_of = [&](int k) { return l_start + dir * (ROW_GROUPS * k + w); };
+    auto row_loaded = [&](int k, int l) { return k < NLOAD && l >= l_first && l <= l_last; };
     auto load_row = [&](int k, V v[9], T &h) {
-        const int l = tl.y0 - 1 + ROW_GROUPS * k + w;
+        const int l = row_of(k);
         if (row_loaded(k, l)) {
             const gptr<const char> rb = f + (unsigned long long)memory_row(l, ny, walls) * RB;
             if (hlane) h = ld_lane<T>(rb, hoff);
@@ -876,7 +906,7 @@ __global__ __launch_bounds__(BLOCK) void fused2_kernel(const InstDev *__restrict
 
 #pragma unroll 4
     for (int k = 0; k < NK; ++k) {
-        const int l = tl.y0 - 1 + ROW_GROUPS * k + w;
+        const int l = row_of(k);
         const bool have = row_loaded(k, l);
         V fq[9];
         T hq = T(0);
@@ -884,7 +914,7 @@ __global__ __launch_bounds__(BLOCK) void fused2_kernel(const InstDev *__restrict
         for (int a = 0; a < 9; ++a) fq[a].x = fq[a].y = T(0);
         load_row(k + 1, fq, hq);
 
-        T *row = ring + ((l + 2 * RING) % RING) * LW;
+        T *row = ring + (l & (RING - 1)) * LW;
         if (have) {
             const T dm_h = halo_density<T>(hn);
             if (hroot) {
@@ -895,11 +925,11 @@ __global__ __launch_bounds__(BLOCK) void fused2_kernel(const InstDev *__restrict
         }
 
         // collide and push the row handled two iterations ago
-        const int c = l - 2 * ROW_GROUPS;
+        const int c = l - dir * 2 * ROW_GROUPS;
         if (k >= 2 && c >= tl.y0 && c < y_end) {
-            const T *rS = ring + ((c - 1 + 2 * RING) % RING) * LW;
-            const T *rC = ring + ((c + 2 * RING) % RING) * LW;
-            const T *rN = ring + ((c + 1 + 2 * RING) % RING) * LW;
+            const T *rS = ring + ((c - 1) & (RING - 1)) * LW;
+            const T *rC = ring + (c & (RING - 1)) * LW;
+            const T *rN = ring + ((c + 1) & (RING - 1)) * LW;
             T v0[9], v1[9];
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
@@ -1271,30 +1301,71 @@ hipError_t collide_dispatch(int variant, const InstDev *di, const Tile *dt, int 
 }
 
 template <typename T, bool E64>
-hipError_t fused_dispatch(int variant, const InstDev *di, const Tile *dt, int nt, int s, hipStream_t st)
+hipError_t fused_dispatch(int variant, const InstDev *di, const Tile *dt, int nt, int s, int alt,
+                          hipStream_t st)
 {
     const dim3 grid(grid_for(nt)), block(BLOCK);
     switch (kVariants[variant].rows) {
-    case 16: fused_kernel<T, E64, 16><<<grid, block, 0, st>>>(di, dt, nt, s); break;
-    case 32: fused_kernel<T, E64, 32><<<grid, block, 0, st>>>(di, dt, nt, s); break;
-    case 64: fused_kernel<T, E64, 64><<<grid, block, 0, st>>>(di, dt, nt, s); break;
-    case 128: fused_kernel<T, E64, 128><<<grid, block, 0, st>>>(di, dt, nt, s); break;
+    case 16: fused_kernel<T, E64, 16><<<grid, block, 0, st>>>(di, dt, nt, s, alt); break;
+    case 32: fused_kernel<T, E64, 32><<<grid, block, 0, st>>>(di, dt, nt, s, alt); break;
+    case 64: fused_kernel<T, E64, 64><<<grid, block, 0, st>>>(di, dt, nt, s, alt); break;
+    case 128: fused_kernel<T, E64, 128><<<grid, block, 0, st>>>(di, dt, nt, s, alt); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 template <typename T, bool E64>
-hipError_t fused2_dispatch(int variant, const InstDev *di, const Tile *dt, int nt, int s, hipStream_t st)
+hipError_t fused2_dispatch(int variant, const InstDev *di, const Tile *dt, int nt, int s, int alt,
+                           hipStream_t st)
 {
     const dim3 grid(grid_for(nt)), block(BLOCK);
     switch (kVariants[variant].rows) {
-    case 16: fused2_kernel<T, E64, 16><<<grid, block, 0, st>>>(di, dt, nt, s); break;
-    case 32: fused2_kernel<T, E64, 32><<<grid, block, 0, st>>>(di, dt, nt, s); break;
-    case 64: fused2_kernel<T, E64, 64><<<grid, block, 0, st>>>(di, dt, nt, s); break;
+    case 16: fused2_kernel<T, E64, 16><<<grid, block, 0, st>>>(di, dt, nt, s, alt); break;
+    case 32: fused2_kernel<T, E64, 32><<<grid, block, 0, st>>>(di, dt, nt, s, alt); break;
+    case 64: fused2_kernel<T, E64, 64><<<grid, block, 0, st>>>(di, dt, nt, s, alt); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// Fused instantiation of a variant (nullptr for the two-pass variants).
+template <typename T, bool E64>
+const void *fused_ptr(int variant)
+{
+    const Variant &v = kVariants[variant];
+    if (v.fused == 1) {
+        switch (v.rows) {
+        case 16: return reinterpret_cast<const void *>(fused_kernel<T, E64, 16>);
+        case 32: return reinterpret_cast<const void *>(fused_kernel<T, E64, 32>);
+        case 64: return reinterpret_cast<const void *>(fused_kernel<T, E64, 64>);
+        case 128: return reinterpret_cast<const void *>(fused_kernel<T, E64, 128>);
+        default: return nullptr;
+        }
+    }
+    if (v.fused == 2) {
+        switch (v.rows) {
+        case 16: return reinterpret_cast<const void *>(fused2_kernel<T, E64, 16>);
+        case 32: return reinterpret_cast<const void *>(fused2_kernel<T, E64, 32>);
+        case 64: return reinterpret_cast<const void *>(fused2_kernel<T, E64, 64>);
+        default: return nullptr;
+        }
+    }
+    return nullptr;
+}
+
+// Blocks of each fused instantiation that the device holds at once, by
+// precision mode and variant (0: not known), filled once by
+// prime_residency() outside any graph capture (the occupancy query is a
+// runtime call).  Only the walk order of the fused kernels depends on it.
+constexpr int kMaxVariants = 16;
+int g_resident[3][kMaxVariants];
+std::once_flag g_resident_once;
+
+int whole_grid_resident(int prec, int variant, int ntiles)
+{
+    if (prec < 0 || prec > 2 || variant < 0 || variant >= kMaxVariants) return 0;
+    return (long long)grid_for(ntiles) <= (long long)g_resident[prec][variant] ? 1 : 0;
 }
 
 template <typename T>
@@ -1332,14 +1403,45 @@ hipError_t launch_collide_stream(int prec, int variant, const InstDev *d_inst, c
     return collide_dispatch<float>(variant, d_inst, d_tiles, ntiles, s, st);
 }
 
+int resident_blocks(int prec, int variant)
+{
+    if (prec < 0 || prec > 2 || variant < 0 || variant >= kMaxVariants) return 0;
+    return g_resident[prec][variant];
+}
+
+void prime_residency()
+{
+    std::call_once(g_resident_once, [] {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            return;
+        }
+        for (int v = 0; v < kNumVariants && v < kMaxVariants; ++v)
+            for (int p = 0; p < 3; ++p) {
+                const void *k = p == LBM_FP64   ? fused_ptr<double, false>(v)
+                                : p == LBM_FP32 ? fused_ptr<float, false>(v)
+                                                : fused_ptr<float, true>(v);
+                int per_cu = 0;
+                if (!k) continue;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, BLOCK, 0) == hipSuccess)
+                    g_resident[p][v] = per_cu * cus;
+                else
+                    (void)hipGetLastError();
+            }
+    });
+}
+
 hipError_t launch_fused(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles, int ntiles,
                         int s, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
     if (kVariants[variant].fused != 1) return hipErrorInvalidValue;
-    if (prec == LBM_FP64) return fused_dispatch<double, false>(variant, d_inst, d_tiles, ntiles, s, st);
-    if (prec == LBM_FP32) return fused_dispatch<float, false>(variant, d_inst, d_tiles, ntiles, s, st);
-    return fused_dispatch<float, true>(variant, d_inst, d_tiles, ntiles, s, st);
+    const int alt = whole_grid_resident(prec, variant, ntiles);
+    if (prec == LBM_FP64) return fused_dispatch<double, false>(variant, d_inst, d_tiles, ntiles, s, alt, st);
+    if (prec == LBM_FP32) return fused_dispatch<float, false>(variant, d_inst, d_tiles, ntiles, s, alt, st);
+    return fused_dispatch<float, true>(variant, d_inst, d_tiles, ntiles, s, alt, st);
 }
 
 hipError_t launch_fused2(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles, int ntiles,
@@ -1347,9 +1449,10 @@ hipError_t launch_fused2(int prec, int variant, const InstDev *d_inst, const Til
 {
     if (ntiles <= 0) return hipSuccess;
     if (kVariants[variant].fused != 2) return hipErrorInvalidValue;
-    if (prec == LBM_FP64) return fused2_dispatch<double, false>(variant, d_inst, d_tiles, ntiles, s, st);
-    if (prec == LBM_FP32) return fused2_dispatch<float, false>(variant, d_inst, d_tiles, ntiles, s, st);
-    return fused2_dispatch<float, true>(variant, d_inst, d_tiles, ntiles, s, st);
+    const int alt = whole_grid_resident(prec, variant, ntiles);
+    if (prec == LBM_FP64) return fused2_dispatch<double, false>(variant, d_inst, d_tiles, ntiles, s, alt, st);
+    if (prec == LBM_FP32) return fused2_dispatch<float, false>(variant, d_inst, d_tiles, ntiles, s, alt, st);
+    return fused2_dispatch<float, true>(variant, d_inst, d_tiles, ntiles, s, alt, st);
 }
 
 hipError_t launch_chunk_end(const InstDev *d_inst, int ninst, hipStream_t st, int *d_status)

@@ -107,6 +107,7 @@ _SIGS = {
                            ctypes.POINTER(ctypes.c_float)],
     "lbm_variant_count": [],
     "lbm_variant_name": [ctypes.c_int],
+    "lbm_resident_blocks": [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
     "lbm_set_variant": [ctypes.c_void_p, ctypes.c_int],
     "lbm_critical_point": [ctypes.c_double] * 3 + [ctypes.POINTER(ctypes.c_double)] * 3,
     "lbm_maxwell": [ctypes.c_double] * 4 + [ctypes.POINTER(ctypes.c_double)] * 3,
@@ -211,6 +212,14 @@ def tile_count(p):
 def variant_names():
     L = lib()
     return [L.lbm_variant_name(i).decode() for i in range(L.lbm_variant_count())]
+
+
+def resident_blocks(precision, variant):
+    """Blocks of a fused variant's kernel the device holds at once (known after
+    the first Sim or Batch is created; 0 for the two-pass variants)."""
+    n = ctypes.c_int()
+    _check(lib().lbm_resident_blocks(_PREC[precision], int(variant), ctypes.byref(n)), "lbm_resident_blocks")
+    return n.value
 
 
 def _dtype(precision):

@@ -107,6 +107,20 @@ def test_invalid_parameters_are_rejected_without_a_device():
         L.maxwell(L.critical_point()[0] * 1.01)
 
 
+def test_resident_blocks_query_without_a_device():
+    """Nothing is known before a handle or batch exists on a device; bad
+    arguments are rejected."""
+    L = pytest.importorskip("paper_1605_01800_amd.lbm")
+    lib = L.lib()
+    n = ctypes.c_int(-1)
+    names = L.variant_names()
+    assert lib.lbm_resident_blocks(1, names.index("fused-64x16"), ctypes.byref(n)) == 0
+    assert n.value == 0
+    for prec, var in ((3, 0), (-1, 0), (0, len(names)), (0, -1)):
+        assert lib.lbm_resident_blocks(prec, var, ctypes.byref(n)) == -1, (prec, var)
+    assert lib.lbm_resident_blocks(0, 0, None) == -1
+
+
 def test_workspace_grows_with_precision_and_grid():
     L = pytest.importorskip("paper_1605_01800_amd.lbm")
     a = L.workspace_bytes(L.make_params(256, 256, T_over_Tc=0.7, precision="fp32"))

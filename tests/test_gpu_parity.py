@@ -218,6 +218,47 @@ def test_batch_equals_alone_bitwise(prec, variant):
     batch.close()
 
 
+@pytest.mark.parametrize("prec,variant", [("fp32", "fused-64x16"), ("fp64", "fused-64x16"),
+                                          ("fp32", "fused2-128x16"), ("fp32_mixed", "fused2-128x16")])
+def test_walk_order_does_not_change_results(prec, variant):
+    """A fused launch whose tiles all fit on the device walks every other band
+    of tiles downwards, a larger one walks them all upwards: the same two
+    instances stepped alone (small launches) and beside a filler grid that
+    makes the launch too large give the same bits."""
+    T6, T8 = coexist.temperature(0.6), coexist.temperature(0.8)
+    specs = [(L.make_params(200, 90, T=T6, walls=True, precision=prec, tau_nu=0.8), [(99.5, 30.0, 20.0)]),
+             (L.make_params(78, 129, T=T8, precision=prec, tau_nu=0.51), [(38.0, 64.0, 15.0)])]
+    v = _variant(variant)
+    alone = []
+    for p, b in specs:
+        s = L.Sim(p)
+        s.set_variant(v)
+        s.init_bubble(b, W=5.0)
+        s.step(150)
+        alone.append(s.populations().cpu())
+        s.close()
+    cap = L.resident_blocks(prec, v)
+    assert cap > 0
+    assert max(L.tile_count(p) for p, _ in specs) <= cap
+    cols = 128 if variant.startswith("fused2") else 64
+    nx = cols * (cap // 64 + 1)                   # 1024 rows: 64 bands of 16
+    fill = L.Sim(L.make_params(nx, 1024, T=T8, precision=prec)).init_bubble([(nx / 2, 512.0, 100.0)], W=5.0)
+    sims = [L.Sim(p).init_bubble(b, W=5.0) for p, b in specs]
+    tiles = sum(L.tile_count(s.params) for s in sims + [fill])
+    assert tiles > cap, (tiles, cap)
+    batch = L.Batch(precision=prec, max_instances=3, max_tiles=tiles)
+    batch.set_variant(v)
+    for s in sims + [fill]:
+        batch.attach(s)
+    batch.step_each([150, 150, 1])
+    batch.sync()
+    for s, a in zip(sims, alone):
+        assert torch.equal(s.populations().cpu(), a)
+    batch.close()
+    for s in sims + [fill]:
+        s.close()
+
+
 def test_paired_variant_rejects_odd_nx():
     p = L.make_params(77, 20, T_over_Tc=0.7, precision="fp32")
     s = L.Sim(p)
