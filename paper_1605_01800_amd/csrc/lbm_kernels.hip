@@ -20,6 +20,7 @@
 // contiguous run of tiles, which keeps halo re-reads in that XCD's L2.
 #include <math.h>
 
+#include <atomic>
 #include <mutex>
 
 #include "lbm_internal.h"
@@ -1358,14 +1359,16 @@ const void *fused_ptr(int variant)
 // precision mode and variant (0: not known), filled once by
 // prime_residency() outside any graph capture (the occupancy query is a
 // runtime call).  Only the walk order of the fused kernels depends on it.
+// Atomic so that lbm_resident_blocks may read it from any thread.
 constexpr int kMaxVariants = 16;
-int g_resident[3][kMaxVariants];
+std::atomic<int> g_resident[3][kMaxVariants];
 std::once_flag g_resident_once;
 
 int whole_grid_resident(int prec, int variant, int ntiles)
 {
     if (prec < 0 || prec > 2 || variant < 0 || variant >= kMaxVariants) return 0;
-    return (long long)grid_for(ntiles) <= (long long)g_resident[prec][variant] ? 1 : 0;
+    return (long long)grid_for(ntiles) <= (long long)g_resident[prec][variant].load(std::memory_order_relaxed)
+               ? 1 : 0;
 }
 
 template <typename T>
@@ -1406,7 +1409,7 @@ hipError_t launch_collide_stream(int prec, int variant, const InstDev *d_inst, c
 int resident_blocks(int prec, int variant)
 {
     if (prec < 0 || prec > 2 || variant < 0 || variant >= kMaxVariants) return 0;
-    return g_resident[prec][variant];
+    return g_resident[prec][variant].load(std::memory_order_relaxed);
 }
 
 void prime_residency()
@@ -1426,7 +1429,7 @@ void prime_residency()
                 int per_cu = 0;
                 if (!k) continue;
                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, BLOCK, 0) == hipSuccess)
-                    g_resident[p][v] = per_cu * cus;
+                    g_resident[p][v].store(per_cu * cus, std::memory_order_relaxed);
                 else
                     (void)hipGetLastError();
             }
