@@ -13,3 +13,36 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert r.returncode != 0
     assert "one GPU" in r.stderr
     assert r.stdout.strip() == ""
+
+
+def _bench_module():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_traffic_record_matches_workload_variant_and_launches():
+    """The committed counter record is for the current kernel source and holds
+    one entry per launch shape it was measured in; nothing is reported for a
+    shape or variant it does not hold."""
+    b = _bench_module()
+    one = b.measured_traffic("laplace_sweep", "fused-64x16", 1)
+    four = b.measured_traffic("laplace_sweep", "fused-64x16", 4)
+    large = b.measured_traffic("collapse_large", "fused2-128x16", 1)
+    model_sweep, model_large = 72 * 24 * 256 * 256, 72 * 8192 * 4096
+    for got, model in ((one, model_sweep), (four, model_sweep), (large, model_large)):
+        assert got is not None
+        assert model <= got < 1.2 * model
+    assert b.measured_traffic("laplace_sweep", "fused-64x16", 2) is None
+    assert b.measured_traffic("laplace_sweep", "fused2-128x16", 1) is None
+    assert b.measured_traffic("single_small", "fused-64x16", 1) is None
+
+
+def test_timing_part_divides_the_steps_within_the_warmup():
+    b = _bench_module()
+    for steps, warmup in ((1280, 256), (50, 10), (10, 2), (7, 0), (100, 3)):
+        part = b.timing_part(steps, warmup)
+        assert steps % part == 0
+        assert warmup == 0 or part <= warmup
