@@ -73,20 +73,29 @@ def percentile(values, q):
 
 
 class GpuBackend:
-    """Backend over liblbm: one lbm.Batch, one lbm.Sim per admitted request."""
+    """Backend over liblbm: one lbm.Sim per admitted request, resident in one
+    of `n_batches` lbm.Batch objects, each on its own stream (default
+    priority).  With several batches their launches overlap, so one batch's
+    start-up, tail and kernel boundary run under another's work; a new
+    request joins the batch with the fewest resident sites.  Results do not
+    depend on the batch a request is in."""
 
     def __init__(self, precision="fp32", device="cuda", max_instances=64, max_tiles=1 << 20,
-                 variant=None, keep_state=False):
+                 variant=None, keep_state=False, n_batches=1):
         from . import lbm
         self.lbm = lbm
         self.precision = precision
         self.device = device
         self.keep_state = keep_state
-        self.batch = lbm.Batch(precision=precision, max_instances=max_instances,
-                               max_tiles=max_tiles, device=device)
+        self.batches = [lbm.Batch(precision=precision, max_instances=max_instances,
+                                  max_tiles=max_tiles, device=device) for _ in range(max(1, int(n_batches)))]
+        self.batch = self.batches[0]
+        self._where = {}                # id(handle) -> its batch
+        self._sites = [0] * len(self.batches)
         self.variant = variant
         if variant is not None:
-            self.batch.set_variant(variant)
+            for b in self.batches:
+                b.set_variant(variant)
         self._bad = {}
 
     def params(self, req):
@@ -105,14 +114,23 @@ class GpuBackend:
         return sim
 
     def attach(self, h):
-        self.batch.attach(h)
+        k = min(range(len(self.batches)), key=lambda i: self._sites[i])
+        self.batches[k].attach(h)
+        self._where[id(h)] = k
+        self._sites[k] += h.nx * h.ny
 
     def step(self, handles, counts):
-        self.batch.step_each(counts)
+        n = {id(h): c for h, c in zip(handles, counts)}
+        for b in self.batches:
+            if b.members:
+                b.step_each([n.get(id(m), 0) for m in b.members])
 
     def sync(self):
-        # one transfer reads every resident request's latch
-        self._bad = {id(m): bad for m, bad in zip(self.batch.members, self.batch.status())}
+        # one transfer per batch reads its resident requests' latches
+        self._bad = {}
+        for b in self.batches:
+            if b.members:
+                self._bad.update({id(m): bad for m, bad in zip(b.members, b.status())})
 
     def failed(self, h):
         return self._bad.get(id(h), False)
@@ -120,7 +138,9 @@ class GpuBackend:
     def finish(self, h):
         out = h.macros(fields=False, check=False)["diag"]
         state = h.populations().cpu() if self.keep_state and not out["nonfinite"] else None
-        self.batch.detach(h)
+        k = self._where.pop(id(h))
+        self.batches[k].detach(h)
+        self._sites[k] -= h.nx * h.ny
         h.close()
         return out, state
 
@@ -138,12 +158,14 @@ class GpuBackend:
         for s in sims:
             s.close()
         self.variant = variant
-        self.batch.set_variant(variant)
+        for b in self.batches:
+            b.set_variant(variant)
         sites = sum(r.sites for r in reqs)
         return variant, sites / (ms * 1e-3) / 1e6
 
     def close(self):
-        self.batch.close()
+        for b in self.batches:
+            b.close()
 
 
 class Server:

@@ -23,10 +23,11 @@ def _requests():
     ]
 
 
-@pytest.mark.parametrize("budget_mb", [1000, 12])
-def test_served_results_equal_alone_bitwise(budget_mb):
+@pytest.mark.parametrize("budget_mb,batches", [(1000, 1), (12, 1), (1000, 3), (12, 2)])
+def test_served_results_equal_alone_bitwise(budget_mb, batches):
     variant = L.variant_names().index("fused-64x16")
-    be = GpuBackend(precision="fp32", max_instances=8, max_tiles=1 << 14, variant=variant, keep_state=True)
+    be = GpuBackend(precision="fp32", max_instances=8, max_tiles=1 << 14, variant=variant, keep_state=True,
+                    n_batches=batches)
     srv = Server(be, budget_bytes=budget_mb * 10 ** 6, max_slots=8, chunk_steps=128)
     results, stats = srv.run(_requests())
     be.close()
@@ -55,7 +56,8 @@ def test_a_failing_request_is_isolated():
     reqs = _requests()[:3] + [
         Request(id=5, nx=90, ny=70, walls=True, T_over_Tc=0.7, steps=900, bubbles=[(44.5, 25.0, 12.0)],
                 delta=1.5, arrival=0.0)]
-    be = GpuBackend(precision="fp32", max_instances=8, max_tiles=1 << 14, variant=variant, keep_state=True)
+    be = GpuBackend(precision="fp32", max_instances=8, max_tiles=1 << 14, variant=variant, keep_state=True,
+                    n_batches=2)
     srv = Server(be, budget_bytes=10 ** 9, max_slots=8, chunk_steps=128)
     results, stats = srv.run(reqs)
     be.close()
