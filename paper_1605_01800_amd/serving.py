@@ -89,7 +89,6 @@ class GpuBackend:
         self.keep_state = keep_state
         self.batches = [lbm.Batch(precision=precision, max_instances=max_instances,
                                   max_tiles=max_tiles, device=device) for _ in range(max(1, int(n_batches)))]
-        self.batch = self.batches[0]
         self._where = {}                # id(handle) -> its batch
         self._sites = [0] * len(self.batches)
         self.variant = variant
