@@ -456,6 +456,8 @@ def main():
             batch.detach(s)
         group = L.BatchGroup(sims, precision=precision, n_batches=n_streams, device=device)
         group.set_variant(variant)
+        group_wt = group.batches[0].write_through
+        workload["write_through"] = group_wt
         ms, median_ms, nparts = timed_region(torch, group, group.streams[0], group, args.steps, args.warmup)
     else:
         ms, median_ms, nparts = ms1, median1, nparts1
@@ -542,7 +544,8 @@ def main():
         c_traffic = measured_traffic(args.workload, vname, n_streams)
         c_achieved = dominant[2] * sites / (step_ms * 1e-3) / 1e9
         out["roofline"]["concurrent_streams"] = {
-            "streams": n_streams, "launches_per_step": n_streams, "step_ms": step_ms,
+            "streams": n_streams, "launches_per_step": n_streams, "write_through": group_wt,
+            "step_ms": step_ms,
             "achieved": round(c_achieved, 1), "frac": round(c_achieved / HBM_PEAK_GBS, 4),
             "frac_of_copy": round(c_achieved / copy_gbs, 4), "traffic": c_traffic,
             "traffic_over_algorithmic": None if c_traffic is None else round(c_traffic / (dominant[2] * sites), 4)}

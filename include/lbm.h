@@ -243,6 +243,16 @@ int lbm_resident_blocks(int precision, int variant, int *blocks);
  * an odd-nx instance to a batch using one; the autotuner skips them then. */
 int lbm_set_variant(void *handle, int variant);
 int lbm_batch_set_variant(void *batch, int variant);
+/* on = 1: the fused single-pass kernel of the 64-column variants ("fused-*")
+ * stores the batch's populations with write-through stores (relaxed
+ * agent-scope atomic stores, which leave no dirty line in the XCD's L2);
+ * 0 (the default): ordinary stores.  Results are bitwise the same.  Every
+ * kernel end writes back the dirty L2 lines of the whole device, so when
+ * several batches run concurrently on their own streams (each launch's end
+ * then also writes back the others' lines) write-through pays; a batch
+ * running alone is faster without it.  The paired and two-pass variants
+ * ignore the setting.  LBM_EINVAL for a null batch or on not 0 or 1. */
+int lbm_batch_set_write_through(void *batch, int on);
 /* Times every variant on the batch's current instances with HIP events, in
  * three passes of min(reps, 8) warm-up steps and reps timed steps each, scores
  * each variant by its fastest pass, selects the best and returns it with its

@@ -133,10 +133,11 @@ struct Stager {
 };
 
 struct GraphKey {
-    int variant, K, ntiles, ninst;
+    int variant, K, ntiles, ninst, write_through;
     bool operator<(const GraphKey &o) const
     {
-        return std::tie(variant, K, ntiles, ninst) < std::tie(o.variant, o.K, o.ntiles, o.ninst);
+        return std::tie(variant, K, ntiles, ninst, write_through) <
+               std::tie(o.variant, o.K, o.ntiles, o.ninst, o.write_through);
     }
 };
 
@@ -177,6 +178,7 @@ struct Batch {
     std::vector<InstDev> descs;   // host copies in attach order
     int ntiles = 0;
     int variant = 0;
+    int write_through = 0;        // fused stores write through L2
     bool dirty = true;
     Stager stager_desc, stager_tiles;
     std::map<GraphKey, hipGraphExec_t> graphs;
@@ -330,13 +332,13 @@ int sync_own(Instance *h, int v = -1)
 
 // Enqueues one chunk: K steps of both passes and the end-of-chunk kernel.
 int enqueue_chunk(int prec, int variant, const InstDev *d_inst, int ninst, const Tile *d_tiles,
-                  int ntiles, int K, hipStream_t st, int *d_status)
+                  int ntiles, int K, hipStream_t st, int *d_status, int write_through)
 {
     for (int s = 0; s < K; ++s) {
         if (kVariants[variant].fused == 2) {
             TRYHIP(launch_fused2(prec, variant, d_inst, d_tiles, ntiles, s, st));
         } else if (kVariants[variant].fused == 1) {
-            TRYHIP(launch_fused(prec, variant, d_inst, d_tiles, ntiles, s, st));
+            TRYHIP(launch_fused(prec, variant, d_inst, d_tiles, ntiles, s, st, write_through));
         } else {
             TRYHIP(launch_psi_pass(prec, variant, d_inst, d_tiles, ntiles, s, st));
             TRYHIP(launch_collide_stream(prec, variant, d_inst, d_tiles, ntiles, s, st));
@@ -348,15 +350,17 @@ int enqueue_chunk(int prec, int variant, const InstDev *d_inst, int ninst, const
 
 // Runs one chunk through a cached graph when the stream can be captured.
 int run_chunk(std::map<GraphKey, hipGraphExec_t> &cache, int prec, int variant, const InstDev *d_inst,
-              int ninst, const Tile *d_tiles, int ntiles, int K, hipStream_t st, int *d_status = nullptr)
+              int ninst, const Tile *d_tiles, int ntiles, int K, hipStream_t st, int *d_status = nullptr,
+              int write_through = 0)
 {
-    if (st == nullptr) return enqueue_chunk(prec, variant, d_inst, ninst, d_tiles, ntiles, K, st, d_status);
-    GraphKey key{variant, K, ntiles, ninst};
+    if (st == nullptr)
+        return enqueue_chunk(prec, variant, d_inst, ninst, d_tiles, ntiles, K, st, d_status, write_through);
+    GraphKey key{variant, K, ntiles, ninst, write_through};
     auto it = cache.find(key);
     if (it == cache.end()) {
         hipGraph_t g = nullptr;
         TRYHIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        int rc = enqueue_chunk(prec, variant, d_inst, ninst, d_tiles, ntiles, K, st, d_status);
+        int rc = enqueue_chunk(prec, variant, d_inst, ninst, d_tiles, ntiles, K, st, d_status, write_through);
         hipError_t e = hipStreamEndCapture(st, &g);
         if (rc != LBM_OK) {
             if (g) (void)hipGraphDestroy(g);
@@ -457,7 +461,7 @@ int batch_run(Batch *b, const std::vector<int64_t> &counts, bool timed, float *m
         if (rc != LBM_OK) break;
         if (!timed) {
             rc = run_chunk(b->graphs, b->precision, b->variant, b->d_descs, n, b->d_tiles, b->ntiles, K,
-                           b->stream, b->d_status);
+                           b->stream, b->d_status, b->write_through);
         } else {
             const bool fused = kVariants[b->variant].fused;
             for (int s = 0; s < K && rc == LBM_OK && fused; ++s) {
@@ -467,7 +471,8 @@ int batch_run(Batch *b, const std::vector<int64_t> &counts, bool timed, float *m
                     if (kVariants[b->variant].fused == 2)
                         rc = hip_ok(launch_fused2(b->precision, b->variant, b->d_descs, b->d_tiles, b->ntiles, s, b->stream));
                     else
-                        rc = hip_ok(launch_fused(b->precision, b->variant, b->d_descs, b->d_tiles, b->ntiles, s, b->stream));
+                        rc = hip_ok(launch_fused(b->precision, b->variant, b->d_descs, b->d_tiles, b->ntiles, s, b->stream,
+                                                 b->write_through));
                 }
                 if (rc == LBM_OK) rc = hip_ok(hipEventRecord(e1, b->stream));
                 if (rc == LBM_OK) rc = hip_ok(hipEventSynchronize(e1));
@@ -1057,6 +1062,14 @@ int lbm_batch_step_timed(void *batch, int64_t n, float *ms)
     Batch *b = (Batch *)batch;
     if (!b || n < 0 || !ms) return LBM_EINVAL;
     return batch_run(b, std::vector<int64_t>(b->members.size(), n), true, ms);
+}
+
+int lbm_batch_set_write_through(void *batch, int on)
+{
+    Batch *b = (Batch *)batch;
+    if (!b || (on != 0 && on != 1)) return LBM_EINVAL;
+    b->write_through = on;
+    return LBM_OK;
 }
 
 int lbm_batch_set_variant(void *batch, int variant)

@@ -121,8 +121,10 @@ hipError_t launch_psi_pass(int prec, int variant, const InstDev *d_inst, const T
                            int ntiles, int s, hipStream_t st);
 hipError_t launch_collide_stream(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles,
                                  int ntiles, int s, hipStream_t st);
+// write_through: the stores of the step write through L2 (see
+// lbm_batch_set_write_through).
 hipError_t launch_fused(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles, int ntiles,
-                        int s, hipStream_t st);
+                        int s, hipStream_t st, int write_through = 0);
 hipError_t launch_fused2(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles, int ntiles,
                          int s, hipStream_t st);
 // End of a chunk: folds the wall-pressure maxima, advances step and parity;

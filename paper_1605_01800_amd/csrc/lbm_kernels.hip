@@ -92,6 +92,16 @@ __device__ __forceinline__ void st(gptr<char> row_base, unsigned lane_off, T v)
     *(gptr<T>)(scalar_base(row_base) + lane_offset(lane_off)) = v;
 }
 
+// Store that, with WT, is a relaxed agent-scope atomic store: a vector store
+// that writes through the XCD's L2, so the line is not left dirty there.
+template <typename T, bool WT>
+__device__ __forceinline__ void stw(gptr<char> row_base, unsigned lane_off, T v)
+{
+    gptr<T> p = (gptr<T>)(scalar_base(row_base) + lane_offset(lane_off));
+    if constexpr (WT) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+}
+
 // Load whose address differs across the wavefront.
 template <typename T>
 __device__ __forceinline__ T ld_lane(gptr<const char> base, unsigned long long off)
@@ -413,7 +423,7 @@ __device__ __forceinline__ void interaction_force(const T *rS, const T *rC, cons
 // fo; x wraps (xe, xw are the wrapped east and west columns); in y the
 // neighbour wraps, or, through a wall, the population returns to (x, y) as
 // the opposite one (halfway bounce-back).
-template <typename T>
+template <typename T, bool WT = false>
 __device__ __forceinline__ void push_store(gptr<char> fo, unsigned long long PB, const T v[9], unsigned xo,
                                            unsigned xeo, unsigned xwo, int y, int ny,
                                            unsigned long long row_bytes, int walls)
@@ -427,26 +437,26 @@ __device__ __forceinline__ void push_store(gptr<char> fo, unsigned long long PB,
     const gptr<char> rc = fo + (unsigned long long)y * row_bytes;
     const gptr<char> rn = fo + (unsigned long long)yn * row_bytes;
     const gptr<char> rs = fo + (unsigned long long)ys * row_bytes;
-    st<T>(rc, xo, v[0]);
-    st<T>(rc + 1 * PB, xeo, v[1]);
-    st<T>(rc + 3 * PB, xwo, v[3]);
+    stw<T, WT>(rc, xo, v[0]);
+    stw<T, WT>(rc + 1 * PB, xeo, v[1]);
+    stw<T, WT>(rc + 3 * PB, xwo, v[3]);
     if (walls && top) {
-        st<T>(rc + 4 * PB, xo, v[2]);
-        st<T>(rc + 7 * PB, xo, v[5]);
-        st<T>(rc + 8 * PB, xo, v[6]);
+        stw<T, WT>(rc + 4 * PB, xo, v[2]);
+        stw<T, WT>(rc + 7 * PB, xo, v[5]);
+        stw<T, WT>(rc + 8 * PB, xo, v[6]);
     } else {
-        st<T>(rn + 2 * PB, xo, v[2]);
-        st<T>(rn + 5 * PB, xeo, v[5]);
-        st<T>(rn + 6 * PB, xwo, v[6]);
+        stw<T, WT>(rn + 2 * PB, xo, v[2]);
+        stw<T, WT>(rn + 5 * PB, xeo, v[5]);
+        stw<T, WT>(rn + 6 * PB, xwo, v[6]);
     }
     if (walls && bot) {
-        st<T>(rc + 2 * PB, xo, v[4]);
-        st<T>(rc + 5 * PB, xo, v[7]);
-        st<T>(rc + 6 * PB, xo, v[8]);
+        stw<T, WT>(rc + 2 * PB, xo, v[4]);
+        stw<T, WT>(rc + 5 * PB, xo, v[7]);
+        stw<T, WT>(rc + 6 * PB, xo, v[8]);
     } else {
-        st<T>(rs + 4 * PB, xo, v[4]);
-        st<T>(rs + 7 * PB, xwo, v[7]);
-        st<T>(rs + 8 * PB, xeo, v[8]);
+        stw<T, WT>(rs + 4 * PB, xo, v[4]);
+        stw<T, WT>(rs + 7 * PB, xwo, v[7]);
+        stw<T, WT>(rs + 8 * PB, xeo, v[8]);
     }
 }
 
@@ -590,7 +600,7 @@ __device__ __forceinline__ int memory_row(int l, int ny, int walls)
 template <typename T, bool EOS64, int H>
 __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict__ insts,
                                                       const Tile *__restrict__ tiles, int ntiles, int s,
-                                                      int alternate)
+                                                      int alternate, int write_through)
 {
     constexpr int RING = 16;
     constexpr int LW = TILE_X + 2;
@@ -707,7 +717,10 @@ __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict_
             T pc, Fx, Fy;
             interaction_force<T>(rS, rC, rN, lane + 1, mG, pc, Fx, Fy);
             collide_site<T>(fb, pc, Fx, Fy, R);
-            push_store<T>(fo, PB, fb, xo, xeo, xwo, c, ny, RB, walls);
+            // write-through stores leave no dirty lines in L2 for the
+            // kernel's end to write back (chosen per batch, uniform)
+            if (write_through) push_store<T, true>(fo, PB, fb, xo, xeo, xwo, c, ny, RB, walls);
+            else push_store<T, false>(fo, PB, fb, xo, xeo, xwo, c, ny, RB, walls);
         }
 
         __syncthreads();
@@ -1303,14 +1316,14 @@ hipError_t collide_dispatch(int variant, const InstDev *di, const Tile *dt, int 
 
 template <typename T, bool E64>
 hipError_t fused_dispatch(int variant, const InstDev *di, const Tile *dt, int nt, int s, int alt,
-                          hipStream_t st)
+                          int wt, hipStream_t st)
 {
     const dim3 grid(grid_for(nt)), block(BLOCK);
     switch (kVariants[variant].rows) {
-    case 16: fused_kernel<T, E64, 16><<<grid, block, 0, st>>>(di, dt, nt, s, alt); break;
-    case 32: fused_kernel<T, E64, 32><<<grid, block, 0, st>>>(di, dt, nt, s, alt); break;
-    case 64: fused_kernel<T, E64, 64><<<grid, block, 0, st>>>(di, dt, nt, s, alt); break;
-    case 128: fused_kernel<T, E64, 128><<<grid, block, 0, st>>>(di, dt, nt, s, alt); break;
+    case 16: fused_kernel<T, E64, 16><<<grid, block, 0, st>>>(di, dt, nt, s, alt, wt); break;
+    case 32: fused_kernel<T, E64, 32><<<grid, block, 0, st>>>(di, dt, nt, s, alt, wt); break;
+    case 64: fused_kernel<T, E64, 64><<<grid, block, 0, st>>>(di, dt, nt, s, alt, wt); break;
+    case 128: fused_kernel<T, E64, 128><<<grid, block, 0, st>>>(di, dt, nt, s, alt, wt); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1437,14 +1450,15 @@ void prime_residency()
 }
 
 hipError_t launch_fused(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles, int ntiles,
-                        int s, hipStream_t st)
+                        int s, hipStream_t st, int write_through)
 {
     if (ntiles <= 0) return hipSuccess;
     if (kVariants[variant].fused != 1) return hipErrorInvalidValue;
     const int alt = whole_grid_resident(prec, variant, ntiles);
-    if (prec == LBM_FP64) return fused_dispatch<double, false>(variant, d_inst, d_tiles, ntiles, s, alt, st);
-    if (prec == LBM_FP32) return fused_dispatch<float, false>(variant, d_inst, d_tiles, ntiles, s, alt, st);
-    return fused_dispatch<float, true>(variant, d_inst, d_tiles, ntiles, s, alt, st);
+    const int wt = write_through ? 1 : 0;
+    if (prec == LBM_FP64) return fused_dispatch<double, false>(variant, d_inst, d_tiles, ntiles, s, alt, wt, st);
+    if (prec == LBM_FP32) return fused_dispatch<float, false>(variant, d_inst, d_tiles, ntiles, s, alt, wt, st);
+    return fused_dispatch<float, true>(variant, d_inst, d_tiles, ntiles, s, alt, wt, st);
 }
 
 hipError_t launch_fused2(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles, int ntiles,

@@ -103,6 +103,7 @@ _SIGS = {
     "lbm_batch_status": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int],
     "lbm_batch_destroy": [ctypes.c_void_p],
     "lbm_batch_set_variant": [ctypes.c_void_p, ctypes.c_int],
+    "lbm_batch_set_write_through": [ctypes.c_void_p, ctypes.c_int],
     "lbm_batch_autotune": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                            ctypes.POINTER(ctypes.c_float)],
     "lbm_variant_count": [],
@@ -415,6 +416,7 @@ class Batch:
                                       ctypes.byref(b)), "lbm_batch_create")
         self.b = b
         self.members = []
+        self.write_through = False
 
     def attach(self, sim):
         _check(lib().lbm_batch_attach(self.b, sim.h), "lbm_batch_attach")
@@ -425,6 +427,13 @@ class Batch:
         _check(lib().lbm_batch_detach(self.b, sim.h), "lbm_batch_detach")
         self.members.remove(sim)
         sim._batch = None
+
+    def set_write_through(self, on):
+        """Write-through population stores in the fused 64-column kernels:
+        faster when several batches run concurrently, slower alone; results
+        are bitwise the same."""
+        _check(lib().lbm_batch_set_write_through(self.b, 1 if on else 0), "lbm_batch_set_write_through")
+        self.write_through = bool(on)
 
     def step(self, n=1):
         _check(lib().lbm_batch_step(self.b, int(n)), "lbm_batch_step")
@@ -484,11 +493,15 @@ class BatchGroup:
     """Independent instances spread round-robin over several batches, each on
     its own stream (default priority), stepped together: the batches' kernels
     run concurrently, so one batch's start-up and tail, and the gap at its
-    kernel boundaries, overlap another's work.  Results are bitwise those of
-    one batch (the same kernels on the same tiles)."""
+    kernel boundaries, overlap another's work.  With more than one batch the
+    batches use write-through stores (Batch.set_write_through), so that each
+    kernel end has little dirty L2 to write back.  Results are bitwise those
+    of one batch (the same kernels on the same tiles)."""
 
-    def __init__(self, sims, precision="fp32", n_batches=4, device="cuda"):
+    def __init__(self, sims, precision="fp32", n_batches=4, device="cuda", write_through=None):
         n = max(1, min(int(n_batches), len(sims)))
+        if write_through is None:
+            write_through = n > 1
         groups = [list(sims[i::n]) for i in range(n)]
         self.batches = []
         for g in groups:
@@ -496,6 +509,7 @@ class BatchGroup:
                       max_tiles=sum(tile_count(s.params) for s in g), device=device)
             for s in g:
                 b.attach(s)
+            b.set_write_through(write_through)
             self.batches.append(b)
 
     @property

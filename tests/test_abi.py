@@ -119,6 +119,7 @@ def test_resident_blocks_query_without_a_device():
     for prec, var in ((3, 0), (-1, 0), (0, len(names)), (0, -1)):
         assert lib.lbm_resident_blocks(prec, var, ctypes.byref(n)) == -1, (prec, var)
     assert lib.lbm_resident_blocks(0, 0, None) == -1
+    assert lib.lbm_batch_set_write_through(None, 1) == -1
 
 
 def test_workspace_grows_with_precision_and_grid():

@@ -247,7 +247,8 @@ def test_collapse_full_horizon_binary32_against_binary64():
 
 def test_batch_group_equals_one_batch_bitwise():
     """The sweep's 24 instances spread over four batches on four streams, as
-    bench.py times them, step bitwise like the same instances in one batch."""
+    bench.py times them (write-through stores), step bitwise like the same
+    instances in one batch."""
     print("case batch group", flush=True)
     out = []
     for n_batches in (1, 4):
@@ -256,6 +257,7 @@ def test_batch_group_equals_one_batch_bitwise():
             runner = _batch(sims, "fp32", "fused-64x16")
         else:
             runner = L.BatchGroup(sims, precision="fp32", n_batches=n_batches)
+            assert runner.batches[0].write_through
             runner.set_variant(L.variant_names().index("fused-64x16"))
         runner.step(300)
         runner.sync()

@@ -259,6 +259,32 @@ def test_walk_order_does_not_change_results(prec, variant):
         s.close()
 
 
+@pytest.mark.parametrize("prec,variant", [("fp64", "fused-64x16"), ("fp32", "fused-64x32"),
+                                          ("fp32_mixed", "fused-64x16"), ("fp32", "fused2-128x16")])
+def test_write_through_stores_do_not_change_results(prec, variant):
+    """A batch with write-through population stores steps bitwise like one
+    without (the paired kernels ignore the setting)."""
+    T6, T8 = coexist.temperature(0.6), coexist.temperature(0.8)
+    specs = [(L.make_params(200, 90, T=T6, walls=True, precision=prec, tau_nu=0.8), [(99.5, 30.0, 20.0)]),
+             (L.make_params(78, 129, T=T8, precision=prec, tau_nu=0.51), [(38.0, 64.0, 15.0)])]
+    out = []
+    for wt in (False, True):
+        sims = [L.Sim(p).init_bubble(b, W=5.0) for p, b in specs]
+        batch = L.Batch(precision=prec, max_instances=2, max_tiles=sum(L.tile_count(p) for p, _ in specs))
+        batch.set_variant(_variant(variant))
+        batch.set_write_through(wt)
+        for s in sims:
+            batch.attach(s)
+        batch.step(140)
+        batch.sync()
+        out.append([s.populations().cpu() for s in sims])
+        batch.close()
+        for s in sims:
+            s.close()
+    for a, b in zip(*out):
+        assert torch.equal(a, b)
+
+
 def test_paired_variant_rejects_odd_nx():
     p = L.make_params(77, 20, T_over_Tc=0.7, precision="fp32")
     s = L.Sim(p)
