@@ -145,6 +145,8 @@ def parse():
     ap.add_argument("--served-budget-gb", type=float, default=8.0)
     ap.add_argument("--served-batches", type=int, default=2,
                     help="batches (one stream each) the served requests are spread over")
+    ap.add_argument("--served-write-through", type=int, default=1, choices=[0, 1],
+                    help="write-through population stores in the served batches")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run liblbm's plain copy kernel over MIB MiB, 5 times, and exit "
                          "(reference for the memory-traffic counters)")
@@ -321,7 +323,7 @@ def fp64_plain(L, device, steps):
     return len(sims) * 256 * 256 * steps / dt / 1e6
 
 
-def served_run(device, n_requests, budget_gb, load=0.8, chunk=500, seed=0, batches=1):
+def served_run(device, n_requests, budget_gb, load=0.8, chunk=500, seed=0, batches=1, write_through=False):
     """The served batch: n_requests requests of the served-batch trace (sides
     log-uniform in [64, 1024], aspect 1, 4/3 or 2, half periodic bubbles and
     half wall-bounded collapses, T/Tc in [0.6, 0.9], 5,000-40,000 steps),
@@ -333,7 +335,7 @@ def served_run(device, n_requests, budget_gb, load=0.8, chunk=500, seed=0, batch
     trace = inputs.request_trace(n_requests, seed)
     reqs0 = serving.make_requests(trace, [0.0] * n_requests)
     be = serving.GpuBackend(precision="fp32", device=device, max_instances=64, max_tiles=1 << 19,
-                            n_batches=batches)
+                            n_batches=batches, write_through=write_through)
     variant, cal_mlups = be.autotune(reqs0[:16])
     work = np.mean([r.sites * r.steps for r in reqs0])
     rate = load * cal_mlups * 1e6 / work
@@ -347,6 +349,7 @@ def served_run(device, n_requests, budget_gb, load=0.8, chunk=500, seed=0, batch
     return {"requests": len(results), "arrival_rate_per_s": round(rate, 3), "load": load,
             "calibrated_mlups": round(cal_mlups, 1), "tile": L.variant_names()[variant],
             "budget_GB": budget_gb, "chunk_steps": chunk, "batches": batches,
+            "write_through": bool(write_through),
             "wall_s": round(stats["wall_s"], 3),
             "busy_s": round(stats["busy_s"], 3), "aggregate_mlups": round(stats["mlups"], 1),
             "busy_mlups": round(stats["busy_mlups"], 1), "p50_s": round(stats["p50_s"], 4),
@@ -561,7 +564,8 @@ def main():
         print("# fp64 plain per-instance %.0f MLUPS" % plain, file=sys.stderr, flush=True)
 
     if args.workload == "laplace_sweep" and not args.no_served:
-        sv = served_run(device, args.served_requests, args.served_budget_gb, batches=args.served_batches)
+        sv = served_run(device, args.served_requests, args.served_budget_gb, batches=args.served_batches,
+                        write_through=bool(args.served_write_through))
         out["served"] = sv
         out["p50_s"] = sv["p50_s"]
         out["p99_s"] = sv["p99_s"]

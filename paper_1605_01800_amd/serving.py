@@ -78,10 +78,11 @@ class GpuBackend:
     priority).  With several batches their launches overlap, so one batch's
     start-up, tail and kernel boundary run under another's work; a new
     request joins the batch with the fewest resident sites.  Results do not
-    depend on the batch a request is in."""
+    depend on the batch a request is in, nor on `write_through` (write-through
+    population stores, Batch.set_write_through)."""
 
     def __init__(self, precision="fp32", device="cuda", max_instances=64, max_tiles=1 << 20,
-                 variant=None, keep_state=False, n_batches=1):
+                 variant=None, keep_state=False, n_batches=1, write_through=False):
         from . import lbm
         self.lbm = lbm
         self.precision = precision
@@ -89,6 +90,8 @@ class GpuBackend:
         self.keep_state = keep_state
         self.batches = [lbm.Batch(precision=precision, max_instances=max_instances,
                                   max_tiles=max_tiles, device=device) for _ in range(max(1, int(n_batches)))]
+        for b in self.batches:
+            b.set_write_through(write_through)
         self._where = {}                # id(handle) -> its batch
         self._sites = [0] * len(self.batches)
         self.variant = variant

@@ -23,11 +23,12 @@ def _requests():
     ]
 
 
-@pytest.mark.parametrize("budget_mb,batches", [(1000, 1), (12, 1), (1000, 3), (12, 2)])
-def test_served_results_equal_alone_bitwise(budget_mb, batches):
+@pytest.mark.parametrize("budget_mb,batches,write_through", [(1000, 1, False), (12, 1, False), (1000, 3, False),
+                                                              (12, 2, True), (1000, 2, True)])
+def test_served_results_equal_alone_bitwise(budget_mb, batches, write_through):
     variant = L.variant_names().index("fused-64x16")
     be = GpuBackend(precision="fp32", max_instances=8, max_tiles=1 << 14, variant=variant, keep_state=True,
-                    n_batches=batches)
+                    n_batches=batches, write_through=write_through)
     srv = Server(be, budget_bytes=budget_mb * 10 ** 6, max_slots=8, chunk_steps=128)
     results, stats = srv.run(_requests())
     be.close()
