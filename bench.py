@@ -8,7 +8,8 @@ slab per temperature), binary32, with the tile variant the autotuner picks
 captured HIP graphs.  A "step" advances all 24 instances by one timestep.  The
 steps are timed twice: as one batch over the tiles of all 24 instances on one
 stream (one launch per step over every site), then spread over four batches on
-four streams whose launches run concurrently (`value`).
+four streams whose launches run concurrently, with write-through population
+stores (`value`).
 
 Prints one JSON line: aggregate MLUPS (million lattice-site updates per second)
 of the concurrent run, the roofline of the dominant kernel from the one-stream
