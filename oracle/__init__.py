@@ -13,9 +13,12 @@ Modules:
                  stability condition (Eq. 9), in mpmath
   diagnostics -- bubble radius, pressure jump, slab densities from rho fields
 
-Parity unpinned: the bubble-radius definition and the wall-pressure peak have
-no value in the paper to check against; only their agreement with the GPU path
-is tested.  The mirror reading of the pseudopotential at solid wall sites is
+The paper defines neither a bubble radius nor a wall-pressure peak, so these
+two outputs follow readings of this project (area-equivalent radius, maximum of
+Eq. 15's pressure on the wall rows); the functions that compute them are pinned
+to geometry and exact arithmetic (squares of known area, fractional sites,
+clipping, nearest-centre ownership, compensated sums), while the readings
+themselves have no value in the paper to check against.  The mirror reading of the pseudopotential at solid wall sites is
 likewise not in the paper; it is pinned only through the symmetry it implies
 (for states uniform in x and at rest, each wall is a plane of mirror symmetry
 of the periodic channel twice as tall).

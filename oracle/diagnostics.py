@@ -5,8 +5,10 @@ pressure jump of the Laplace law (Eq. 17) but not how a radius or the two
 pressures are sampled from a diffuse interface; the readings used here are:
 
   radius  -- area-equivalent radius sqrt(A / pi), A = sum of the gas fraction
-             clip((rho_l - rho) / (rho_l - rho_g), 0, 1) over the nodes
-             (parity unpinned: no value in the paper to compare against)
+             clip((rho_l - rho) / (rho_l - rho_g), 0, 1) over the nodes; with
+             several bubbles each node counts for the nearest initial centre
+             (the reading has no value in the paper to compare against; the
+             code is pinned to gas regions of known area)
   p_in    -- mean pressure over nodes closer than R - 2W to the centre
   p_out   -- mean pressure over nodes farther than R + 2W from the centre
   slab    -- densities averaged over the 17 central rows of each phase

@@ -5,6 +5,11 @@ dropped term, a wrong sign, coefficient, index or direction), compiles it with
 the oracle's flags, and runs the oracle's own tests (tests/test_oracle_*.py)
 against it in a separate process: a pin must fail for every mistake.  The
 oracle source itself is not changed; the copy is loaded through ORACLE_LIB.
+
+The post-processing of oracle/diagnostics.py (bubble radius, ownership of
+sites by bubbles, compensated sums, pressure jump, slab densities) is checked
+the same way: a copy with one planted mistake is loaded through
+ORACLE_DIAGNOSTICS by its pins (tests/test_oracle_diagnostics.py).
 """
 import os
 import subprocess
@@ -81,6 +86,41 @@ MUTANTS = [
 ]
 
 
+# (name, text in oracle/diagnostics.py, the mistaken text); each text occurs once
+PY_MUTANTS = [
+    ("radius_sqrt_area_over_pi",    # sqrt(A) / pi instead of sqrt(A / pi)
+     "math.sqrt(float(np.sum(gas_fraction(rho, rho_l, rho_g))) / math.pi)",
+     "math.sqrt(float(np.sum(gas_fraction(rho, rho_l, rho_g)))) / math.pi"),
+    ("gas_fraction_not_clipped",    # fraction outside [0, 1] counted
+     "return np.clip((rho_l - rho) / (rho_l - rho_g), 0.0, 1.0)",
+     "return (rho_l - rho) / (rho_l - rho_g)"),
+    ("gas_fraction_densities_swapped",
+     "return np.clip((rho_l - rho) / (rho_l - rho_g), 0.0, 1.0)",
+     "return np.clip((rho_g - rho) / (rho_g - rho_l), 0.0, 1.0)"),
+    ("radii_farthest_centre",       # each site counted for the farthest centre
+     "owner = np.argmin(d2, axis=0)",
+     "owner = np.argmax(d2, axis=0)"),
+    ("radii_distance_in_x_only",
+     "(xx - cx) ** 2 + (yy - cy) ** 2",
+     "(xx - cx) ** 2"),
+    ("radii_sqrt_area_over_pi",
+     "math.sqrt(float(np.sum(frac[owner == k])) / math.pi)",
+     "math.sqrt(float(np.sum(frac[owner == k]))) / math.pi"),
+    ("kahan_instead_of_neumaier",   # compensation without Neumaier's branch
+     "        if abs(s) >= abs(v):\n            c += (s - t) + v\n        else:\n            c += (v - t) + s\n",
+     "        c += (s - t) + v\n"),
+    ("pressure_jump_sign",          # p_out - p_in, negative for a bubble
+     "return p_in - p_out, p_in, p_out",
+     "return p_out - p_in, p_in, p_out"),
+    ("pressure_jump_band",          # inner sample reaching into the interface
+     "p_in = float(np.mean(p[r < R - 2 * W]))",
+     "p_in = float(np.mean(p[r < R - W]))"),
+    ("slab_sixteen_rows",           # 16 rows instead of the 17 central ones
+     "rows_l = [(liquid_mid + k) % ny for k in range(-8, 9)]",
+     "rows_l = [(liquid_mid + k) % ny for k in range(-8, 8)]"),
+]
+
+
 def _source():
     with open(obuild.SRC) as fh:
         return fh.read()
@@ -94,9 +134,37 @@ def _run_pins(lib_path):
     return subprocess.run(cmd, cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
 
 
+def _py_source():
+    with open(os.path.join(ROOT, "oracle", "diagnostics.py")) as fh:
+        return fh.read()
+
+
+def _run_py_pins(path):
+    env = dict(os.environ, ORACLE_DIAGNOSTICS=path)
+    cmd = [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
+           os.path.join(ROOT, "tests", "test_oracle_diagnostics.py")]
+    return subprocess.run(cmd, cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+
+
+def _survivors(runs):
+    survivors = []
+    for name, r in runs.items():
+        tail = r.stdout.strip().splitlines()[-1] if r.stdout.strip() else r.stderr[-300:]
+        print(name, "->", tail)
+        # exit status 1 with a failed test: a pin caught it (2 and up would be
+        # a collection or usage error, which proves nothing)
+        if not (r.returncode == 1 and "failed" in tail):
+            survivors.append((name, r.returncode, tail))
+    return survivors
+
+
 def test_every_mutation_applies_once():
     src = _source()
     for name, old, new in MUTANTS:
+        assert src.count(old) == 1, name
+        assert old != new, name
+    src = _py_source()
+    for name, old, new in PY_MUTANTS:
         assert src.count(old) == 1, name
         assert old != new, name
 
@@ -114,12 +182,22 @@ def test_every_planted_mistake_fails_a_pin(tmp_path):
         runs = dict(zip(libs, pool.map(_run_pins, libs.values())))
     control = runs.pop("faithful_copy")
     assert control.returncode == 0, control.stdout[-2000:]
-    survivors = []
-    for name, r in runs.items():
-        tail = r.stdout.strip().splitlines()[-1] if r.stdout.strip() else r.stderr[-300:]
-        print(name, "->", tail)
-        # exit status 1 with a failed test: a pin caught it (2 and up would be
-        # a collection or usage error, which proves nothing)
-        if not (r.returncode == 1 and "failed" in tail):
-            survivors.append((name, r.returncode, tail))
+    survivors = _survivors(runs)
+    assert not survivors, survivors
+
+
+def test_every_planted_diagnostics_mistake_fails_a_pin(tmp_path):
+    """The same for oracle/diagnostics.py: every mutant fails a pin of
+    tests/test_oracle_diagnostics.py, and a faithful copy passes them."""
+    src = _py_source()
+    files = {}
+    for name, old, new in PY_MUTANTS + [("faithful_copy", "", "")]:
+        p = tmp_path / (name + ".py")
+        p.write_text(src.replace(old, new) if old else src)
+        files[name] = str(p)
+    with ThreadPoolExecutor(max_workers=4) as pool:
+        runs = dict(zip(files, pool.map(_run_py_pins, files.values())))
+    control = runs.pop("faithful_copy")
+    assert control.returncode == 0, control.stdout[-2000:]
+    survivors = _survivors(runs)
     assert not survivors, survivors
