@@ -42,46 +42,66 @@ BYTES_COLLIDE = {4: 9 * 4 + 4 + 9 * 4, 8: 9 * 8 + 8 + 9 * 8}
 BYTES_FUSED = {4: 18 * 4, 8: 18 * 8}
 
 
-def timing_part(steps, warmup):
-    """Steps per timed part: the largest divisor of `steps` between steps / 20
-    and steps / 5 (5 to 20 parts for a median) that is at most `warmup` (so
-    that the warm-up captures the part's graph before the timed region); else
-    the largest divisor up to `warmup`; `steps` without a warm-up."""
-    if warmup < 1:
-        return steps
-    divisors = [d for d in range(1, steps + 1) if steps % d == 0 and d <= warmup]
-    small = [d for d in divisors if 5 * d <= steps and 20 * d >= steps]
-    return max(small) if small else max(divisors)
+def timing_parts(steps):
+    """Step counts of the timed parts: 256 steps each (the longest chunk one
+    captured graph holds) and the remainder, so that every part replays graphs
+    prepared during the warm-up and the steps need no host-to-device transfer
+    (the descriptors already hold the parts' chunk length)."""
+    full, rest = divmod(steps, 256)
+    return [256] * full + ([rest] if rest else [])
+
+
+_SLEEP_CYCLES_PER_MS = None
+
+
+def gate(torch, stream, ms):
+    """Holds `stream` for about `ms` milliseconds with a spin kernel, so that
+    the host has enqueued the whole timed region (graph launches on every
+    stream, events) before the GPU reaches its first event: the region then
+    times the device work alone, not the host's enqueueing.  The spin kernel
+    runs before the region's first event."""
+    global _SLEEP_CYCLES_PER_MS
+    with torch.cuda.stream(stream):
+        if _SLEEP_CYCLES_PER_MS is None:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            torch.cuda._sleep(1000000)
+            e1.record(stream)
+            e1.synchronize()
+            _SLEEP_CYCLES_PER_MS = 1000000 / max(e0.elapsed_time(e1), 1e-3)
+        torch.cuda._sleep(int(ms * _SLEEP_CYCLES_PER_MS))
 
 
 def timed_region(torch, runner, main, group, steps, warmup):
     """Times `steps` steps of `runner` (a Batch, or a BatchGroup given also as
     `group`) with HIP events on stream `main`; returns (ms, median ms per step
-    of the parts, parts).  The timed steps run as equal parts with events
-    between them (the whole region gives the time; the parts give a median),
-    the warm-up in pieces of the same size so that their graphs are captured
-    beforehand.  With several streams every part starts after the previous
-    one has ended on all of them (fork from and join into `main`)."""
-    part = timing_part(steps, warmup)
-    done = 0
-    while done < warmup:
-        n = min(part, warmup - done)
-        runner.step(n)
-        done += n
+    of the parts, parts).  The warm-up runs `warmup` steps, then readies the
+    timed steps' graphs and descriptors without running them
+    (lbm_batch_prepare), so the timed region enqueues nothing but graph
+    launches.  The timed steps run as parts of up to 256 steps with events
+    between them (the whole region gives the time; the parts give a median).
+    With several streams every part starts after the previous one has ended
+    on all of them (fork from and join into `main`)."""
+    parts = timing_parts(steps)
+    if warmup > 0:
+        runner.step(warmup)
+    runner.prepare(steps)
     runner.sync()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps // part + 1)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(parts) + 1)]
     torch.cuda.synchronize()
+    n_streams = len(group.batches) if group is not None else 1
+    gate(torch, main, max(1.0, 0.25 * len(parts) * n_streams))
     ev[0].record(main)
-    for i in range(1, len(ev)):
+    for i, n in enumerate(parts, start=1):
         if group is not None:
             group.fork(ev[i - 1])
-        runner.step(part)
+        runner.step(n)
         if group is not None:
             group.join(main)
         ev[i].record(main)
     ev[-1].synchronize()
     ms = ev[0].elapsed_time(ev[-1])
-    part_ms = sorted(ev[i - 1].elapsed_time(ev[i]) / part for i in range(1, len(ev)))
+    part_ms = sorted(ev[i - 1].elapsed_time(ev[i]) / n for i, n in enumerate(parts, start=1))
     torch.cuda.synchronize()
     return ms, part_ms[len(part_ms) // 2], len(part_ms)
 
@@ -201,7 +221,7 @@ def collapse_large_sims(L, precision, device):
     from paper_1605_01800_amd import inputs
     nx, ny = 8192, 4096
     bub = inputs.non_overlapping_discs(nx, ny, [300, 200, 150], W=5.0, seed=0, walls=True)
-    p = L.make_params(nx, ny, T_over_Tc=0.6, walls=True, precision=precision, tau_nu=0.51)
+    p = L.make_params(nx, ny, T_over_Tc=0.6, walls=True, precision=precision, tau_nu=0.6)
     s = L.Sim(p, device=device)
     s.init_bubble(bub, W=5.0, delta=0.02)
     return [s]
@@ -414,7 +434,7 @@ def main():
         sims = collapse_large_sims(L, precision, device)
         workload = {"workload": "collapse_large", "instances": 1, "grid": "8192x4096",
                     "walls_y": True, "T_over_Tc": 0.6, "radii": [300, 200, 150], "delta": 0.02,
-                    "tau_nu": 0.51, "eps": 1.86}
+                    "tau_nu": 0.6, "eps": 1.86}
     sites = sum(s.nx * s.ny for s in sims)
     max_tiles = sum(L.tile_count(s.params) for s in sims)
     batch = L.Batch(precision=precision, max_instances=len(sims), max_tiles=max_tiles, device=device)
@@ -472,11 +492,13 @@ def main():
                                                                         ms / args.steps, mlups),
           file=sys.stderr, flush=True)
 
-    # Dominant kernel.  Fused variants launch one kernel per step, so on one
-    # stream a launch lasts the timed region over the step count (an upper
-    # bound: it includes the gaps between launches and one end-of-chunk
-    # kernel per 256 steps) and moves the bytes of all sites.  Two-pass
-    # variants time each launch with its own event pair on the batch's stream.
+    # Dominant kernel.  Fused variants launch one kernel per step, replayed
+    # back to back from prepared graphs, so on one stream a launch lasts the
+    # timed region over the step count (an upper bound: it includes the
+    # kernel boundaries and one end-of-chunk kernel per graph) and moves the
+    # bytes of all sites; a kernel trace of the same command gives the same
+    # average launch.  Two-pass variants time each launch with its own event
+    # pair on the batch's stream.
     nk = min(args.steps, 100)
     if group is not None:
         group.close()
@@ -503,6 +525,12 @@ def main():
                                                                      dominant[2]), file=sys.stderr, flush=True)
 
     traffic = measured_traffic(args.workload, vname, 1)
+    # The MI355X's Infinity Cache (256 MB) sits between the L2s and HBM: a
+    # working set that fits it is served from there, and the FETCH_SIZE and
+    # WRITE_SIZE counters (L2 to fabric) then count cache bytes, not only
+    # DRAM bytes.
+    working_set = sum(L.workspace_bytes(s.params) for s in sims)
+    cache_resident = working_set < 256e6
     copy_gbs = copy_rate(L, dominant[2] * sites // 2, batch.stream)
     out = {
         "metric": "aggregate MLUPS + %HBM roofline (FP32 batched vs FP64 plain); p50/p99 latency",
@@ -529,6 +557,12 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "launch_ms": dominant[1],
             "traffic": traffic,
+            "traffic_counters": "FETCH_SIZE + WRITE_SIZE per launch, scaled by a copy of known size: "
+                                "bytes from the L2s to the fabric" +
+                                (" (the working set fits the 256 MB Infinity Cache, so not all of "
+                                 "them reach DRAM)" if cache_resident else ""),
+            "working_set_bytes": working_set,
+            "cache_resident": cache_resident,
             "bytes_per_site": dominant[2],
             "algorithmic_bytes_per_launch": dominant[2] * sites,
             "traffic_over_algorithmic": None if traffic is None else round(traffic / (dominant[2] * sites), 4),

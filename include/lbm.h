@@ -209,6 +209,18 @@ int lbm_batch_step(void *batch, int64_t n);
  * instance (attach order); instances with fewer steps finish first and stay
  * unchanged afterwards.  Asynchronous. */
 int lbm_batch_step_each(void *batch, const int64_t *counts, int n_counts);
+/* Readies the batch for a following lbm_batch_step(batch, n): the descriptors
+ * of the attached instances and the tile list are sent to the device as that
+ * call needs them, and the HIP graphs of its chunks (the time integration of
+ * Eq. 5 repeated, up to 256 steps per graph) are captured, instantiated and
+ * uploaded.  Enqueues transfers but no kernel and does not advance the state.
+ * The step then enqueues nothing but its graph launches, as long as nothing
+ * that changes the batch (attach, detach, variant, initialisation, another
+ * step count) comes between the two calls; otherwise the step does the
+ * missing work itself.  Meant for timing and for latency-critical loops.
+ * LBM_EINVAL for a null batch or n < 0; LBM_ENOMEM if the tiles exceed the
+ * batch's max_tiles. */
+int lbm_batch_prepare(void *batch, int64_t n);
 int lbm_batch_size(void *batch, int *n_attached);
 /* Non-blocking completion query of the batch's stream, as lbm_poll. */
 int lbm_batch_poll(void *batch, int *done);

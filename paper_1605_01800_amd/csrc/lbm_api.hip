@@ -176,6 +176,11 @@ struct Batch {
     int *d_status;                // latch of each member at the last chunk end
     std::vector<Instance *> members;
     std::vector<InstDev> descs;   // host copies in attach order
+    // What the device descriptors hold: the last upload, advanced like the
+    // end-of-chunk kernel advances them; an upload happens only when the
+    // host copies differ from it.
+    std::vector<InstDev> dev;
+    bool dev_valid = false;
     int ntiles = 0;
     int variant = 0;
     int write_through = 0;        // fused stores write through L2
@@ -348,13 +353,13 @@ int enqueue_chunk(int prec, int variant, const InstDev *d_inst, int ninst, const
     return LBM_OK;
 }
 
-// Runs one chunk through a cached graph when the stream can be captured.
-int run_chunk(std::map<GraphKey, hipGraphExec_t> &cache, int prec, int variant, const InstDev *d_inst,
-              int ninst, const Tile *d_tiles, int ntiles, int K, hipStream_t st, int *d_status = nullptr,
-              int write_through = 0)
+// The cached graph of one chunk of K steps, captured, instantiated and
+// uploaded to the device the first time it is asked for (st must not be the
+// null stream, which cannot be captured).
+int chunk_graph(std::map<GraphKey, hipGraphExec_t> &cache, int prec, int variant, const InstDev *d_inst,
+                int ninst, const Tile *d_tiles, int ntiles, int K, hipStream_t st, int *d_status,
+                int write_through, hipGraphExec_t *out)
 {
-    if (st == nullptr)
-        return enqueue_chunk(prec, variant, d_inst, ninst, d_tiles, ntiles, K, st, d_status, write_through);
     GraphKey key{variant, K, ntiles, ninst, write_through};
     auto it = cache.find(key);
     if (it == cache.end()) {
@@ -372,8 +377,23 @@ int run_chunk(std::map<GraphKey, hipGraphExec_t> &cache, int prec, int variant, 
         (void)hipGraphDestroy(g);
         TRYHIP(e);
         it = cache.emplace(key, ex).first;
+        // the first launch would otherwise copy the graph's launch data
+        TRYHIP(hipGraphUpload(ex, st));
     }
-    TRYHIP(hipGraphLaunch(it->second, st));
+    *out = it->second;
+    return LBM_OK;
+}
+
+// Runs one chunk through a cached graph when the stream can be captured.
+int run_chunk(std::map<GraphKey, hipGraphExec_t> &cache, int prec, int variant, const InstDev *d_inst,
+              int ninst, const Tile *d_tiles, int ntiles, int K, hipStream_t st, int *d_status = nullptr,
+              int write_through = 0)
+{
+    if (st == nullptr)
+        return enqueue_chunk(prec, variant, d_inst, ninst, d_tiles, ntiles, K, st, d_status, write_through);
+    hipGraphExec_t ex = nullptr;
+    TRY(chunk_graph(cache, prec, variant, d_inst, ninst, d_tiles, ntiles, K, st, d_status, write_through, &ex));
+    TRYHIP(hipGraphLaunch(ex, st));
     return LBM_OK;
 }
 
@@ -424,12 +444,35 @@ int batch_sync(Batch *b)
         TRYHIP(hipMemsetAsync(b->d_status, 0, sizeof(int) * (size_t)b->max_inst, b->stream));
         if (!tl.empty()) TRY(b->stager_tiles.upload(b->d_tiles, tl.data(), sizeof(Tile) * tl.size(), b->stream));
         b->dirty = false;
+        b->dev_valid = false;
     } else {
         for (size_t i = 0; i < b->members.size(); ++i) b->descs[i] = b->members[i]->desc;
     }
-    if (!b->descs.empty())
+    // The end-of-chunk kernel advances step and buffer parity on the device
+    // as the host mirrors do, so consecutive chunks of the same length need
+    // no transfer; anything else (a new chunk length, an instance
+    // re-initialised or loaded) differs from the device image and is sent.
+    const bool same = b->dev_valid && b->dev.size() == b->descs.size() &&
+                      memcmp(b->dev.data(), b->descs.data(), sizeof(InstDev) * b->descs.size()) == 0;
+    if (!b->descs.empty() && !same) {
         TRY(b->stager_desc.upload(b->d_descs, b->descs.data(), sizeof(InstDev) * b->descs.size(), b->stream));
+        b->dev = b->descs;
+        b->dev_valid = true;
+    }
     return LBM_OK;
+}
+
+// Sets every member's chunk length for the next chunk of a run whose
+// remaining counts are rem; returns the chunk's step count K.
+int plan_chunk(Batch *b, const std::vector<int64_t> &rem)
+{
+    int K = 0;
+    for (size_t i = 0; i < b->members.size(); ++i) {
+        const int ni = (int)std::min<int64_t>(rem[i], MAX_CHUNK);
+        b->members[i]->desc.n_chunk = ni;
+        K = std::max(K, ni);
+    }
+    return K;
 }
 
 // Steps the members by counts[i] steps each, MAX_CHUNK steps per chunk.
@@ -450,12 +493,7 @@ int batch_run(Batch *b, const std::vector<int64_t> &counts, bool timed, float *m
     }
     int rc = LBM_OK;
     for (;;) {
-        int K = 0;
-        for (int i = 0; i < n; ++i) {
-            const int ni = (int)std::min<int64_t>(rem[i], MAX_CHUNK);
-            b->members[i]->desc.n_chunk = ni;
-            K = std::max(K, ni);
-        }
+        const int K = plan_chunk(b, rem);
         if (K == 0) break;
         rc = batch_sync(b);
         if (rc != LBM_OK) break;
@@ -501,6 +539,7 @@ int batch_run(Batch *b, const std::vector<int64_t> &counts, bool timed, float *m
             Instance *h = b->members[i];
             const int ni = h->desc.n_chunk;
             advance_mirror(h->desc, ni);
+            advance_mirror(b->dev[i], ni);   // what the end-of-chunk kernel did
             rem[i] -= ni;
             h->desc_dirty = true;    // the instance's own descriptor copy is stale
         }
@@ -1055,6 +1094,28 @@ int lbm_batch_step_each(void *batch, const int64_t *counts, int n_counts)
     for (int64_t v : c)
         if (v < 0) return LBM_EINVAL;
     return batch_run(b, c, false, nullptr);
+}
+
+int lbm_batch_prepare(void *batch, int64_t n)
+{
+    Batch *b = (Batch *)batch;
+    if (!b || n < 0) return LBM_EINVAL;
+    if (b->stream == nullptr) return LBM_OK;          // the null stream launches directly
+    const int m = (int)b->members.size();
+    std::vector<int64_t> rem(m, n);
+    const int K = plan_chunk(b, rem);
+    int rc = K > 0 ? batch_sync(b) : LBM_OK;
+    // the graphs of the run's chunk lengths: full chunks and the last one
+    const int tail = (int)(n % MAX_CHUNK);
+    hipGraphExec_t ex = nullptr;
+    if (rc == LBM_OK && n >= MAX_CHUNK)
+        rc = chunk_graph(b->graphs, b->precision, b->variant, b->d_descs, m, b->d_tiles, b->ntiles, MAX_CHUNK,
+                         b->stream, b->d_status, b->write_through, &ex);
+    if (rc == LBM_OK && tail > 0)
+        rc = chunk_graph(b->graphs, b->precision, b->variant, b->d_descs, m, b->d_tiles, b->ntiles, tail,
+                         b->stream, b->d_status, b->write_through, &ex);
+    for (Instance *h : b->members) h->desc.n_chunk = 0;
+    return rc;
 }
 
 int lbm_batch_step_timed(void *batch, int64_t n, float *ms)

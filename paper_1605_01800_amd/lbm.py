@@ -7,7 +7,6 @@ importing this module on a machine without it raises, it never falls back to
 another implementation.
 """
 import ctypes
-import math
 import os
 
 import torch
@@ -97,6 +96,7 @@ _SIGS = {
     "lbm_batch_detach": [ctypes.c_void_p, ctypes.c_void_p],
     "lbm_batch_step": [ctypes.c_void_p, ctypes.c_int64],
     "lbm_batch_step_each": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int],
+    "lbm_batch_prepare": [ctypes.c_void_p, ctypes.c_int64],
     "lbm_batch_step_timed": [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_float)],
     "lbm_batch_size": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)],
     "lbm_batch_poll": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)],
@@ -438,6 +438,11 @@ class Batch:
     def step(self, n=1):
         _check(lib().lbm_batch_step(self.b, int(n)), "lbm_batch_step")
 
+    def prepare(self, n):
+        """Readies a following step(n) so that it enqueues only its graph
+        launches: descriptors sent, chunk graphs captured and uploaded."""
+        _check(lib().lbm_batch_prepare(self.b, int(n)), "lbm_batch_prepare")
+
     def step_each(self, counts):
         arr = (ctypes.c_int64 * max(1, len(counts)))(*[int(c) for c in counts])
         _check(lib().lbm_batch_step_each(self.b, arr, len(counts)), "lbm_batch_step_each")
@@ -524,6 +529,10 @@ class BatchGroup:
         for b in self.batches:
             b.step(n)
 
+    def prepare(self, n):
+        for b in self.batches:
+            b.prepare(n)
+
     def fork(self, event):
         """Makes every batch's stream wait for `event` (recorded by the caller)."""
         for st in self.streams:
@@ -558,6 +567,3 @@ def copy_kernel(dst, src, nbytes, stream=None):
     s = stream.cuda_stream if stream is not None else torch.cuda.current_stream().cuda_stream
     _check(lib().lbm_copy_kernel(dst.data_ptr(), src.data_ptr(), int(nbytes), s), "lbm_copy_kernel")
 
-
-def radius_from_area(area):
-    return math.sqrt(area / math.pi)

@@ -40,9 +40,12 @@ def test_traffic_record_matches_workload_variant_and_launches():
     assert b.measured_traffic("single_small", "fused-64x16", 1) is None
 
 
-def test_timing_part_divides_the_steps_within_the_warmup():
+def test_timing_parts_cover_the_steps_in_whole_graphs():
+    """The timed parts add up to exactly the timed steps, none longer than one
+    captured graph (256 steps), and none depends on the warm-up length."""
     b = _bench_module()
-    for steps, warmup in ((1280, 256), (50, 10), (10, 2), (7, 0), (100, 3)):
-        part = b.timing_part(steps, warmup)
-        assert steps % part == 0
-        assert warmup == 0 or part <= warmup
+    for steps in (1280, 20, 1, 255, 256, 257, 1000):
+        parts = b.timing_parts(steps)
+        assert sum(parts) == steps
+        assert all(0 < n <= 256 for n in parts)
+        assert all(n == 256 for n in parts[:-1])

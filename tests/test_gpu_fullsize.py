@@ -78,7 +78,7 @@ def test_collapse_large_full_size_sampled_windows(prec, variant):
     print("case large", prec, variant, flush=True)
     nx, ny = 8192, 4096
     bub = inputs.non_overlapping_discs(nx, ny, [300, 200, 150], W=5.0, seed=0, walls=True)
-    p = L.make_params(nx, ny, T_over_Tc=0.6, walls=True, precision=prec, tau_nu=0.51)
+    p = L.make_params(nx, ny, T_over_Tc=0.6, walls=True, precision=prec, tau_nu=0.6)
     sim = L.Sim(p)
     sim.init_bubble(bub, W=5.0, delta=0.02)
     b = _batch([sim], prec, variant)
