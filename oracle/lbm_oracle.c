@@ -314,12 +314,42 @@ static int all_finite(const double *v, long n)
     return 1;
 }
 
+/* Largest pressure of Eq. 15 over the two wall rows (y = 0 and y = ny-1) of
+ * a density field: the wall-pressure reading of the collapse runs (the paper
+ * plots a wall pressure but does not define a sampled value). */
+static double wall_row_pressure_max(const oracle_params *P, const double *rho)
+{
+    double best = -INFINITY;
+    const int rows[2] = {0, P->ny - 1};
+    for (int k = 0; k < 2; ++k)
+        for (int x = 0; x < P->nx; ++x) {
+            double pw = oracle_eos_pressure(P, rho[(long)rows[k] * P->nx + x]);
+            if (pw > best) best = pw;
+        }
+    return best;
+}
+
+static int run_steps(const oracle_params *P, double *f, int64_t nsteps, double *wall_p);
+
 /* nsteps full timesteps in place on f (post-streaming populations).  The
  * order within a step: rho and psi of every node (Eqs. 15, 13), the force of
  * every node (Eq. 7), the collision of every node (Eqs. 6, 4, 14, 3), then
  * streaming (Eq. 5).  Returns ORACLE_ENONFINITE, and stops, at the first step
  * whose psi or populations are not finite. */
 int oracle_step(const oracle_params *P, double *f, int64_t nsteps)
+{
+    return run_steps(P, f, nsteps, NULL);
+}
+
+/* The same steps, also writing to wall_p[t] (t = 0 .. nsteps-1) the largest
+ * pressure of Eq. 15 on the wall rows of the state at the start of step t. */
+int oracle_step_wall_pressure(const oracle_params *P, double *f, int64_t nsteps, double *wall_p)
+{
+    if (!wall_p) return ORACLE_EINVAL;
+    return run_steps(P, f, nsteps, wall_p);
+}
+
+static int run_steps(const oracle_params *P, double *f, int64_t nsteps, double *wall_p)
 {
     if (P->nx < 1 || P->ny < 1 || nsteps < 0) return ORACLE_EINVAL;
     long n = (long)P->nx * P->ny;
@@ -333,6 +363,7 @@ int oracle_step(const oracle_params *P, double *f, int64_t nsteps)
     ensure_minv();
     for (int64_t t = 0; t < nsteps; ++t) {
         oracle_density(P, f, rho);
+        if (wall_p) wall_p[t] = wall_row_pressure_max(P, rho);
 #pragma omp parallel for schedule(static)
         for (long i = 0; i < n; ++i) psi[i] = oracle_psi(P, rho[i]);
         if (!all_finite(psi, n)) { rc = ORACLE_ENONFINITE; goto done; }

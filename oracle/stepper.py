@@ -47,6 +47,8 @@ def lib():
         L.oracle_stream.argtypes = [P, dp, dp]
         L.oracle_step.argtypes = [P, dp, ctypes.c_int64]
         L.oracle_step.restype = ctypes.c_int
+        L.oracle_step_wall_pressure.argtypes = [P, dp, ctypes.c_int64, dp]
+        L.oracle_step_wall_pressure.restype = ctypes.c_int
         L.oracle_macros.argtypes = [P, dp, dp, dp, dp, dp]
         L.oracle_macros.restype = ctypes.c_int
         L.oracle_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
@@ -171,6 +173,16 @@ def step(P, f, nsteps=1):
     the oracle's status (0, or -4 for a non-finite state)."""
     assert f.shape == (P.ny, P.nx, 9)
     return lib().oracle_step(ctypes.byref(P), _ptr(f), int(nsteps))
+
+
+def step_wall_pressure(P, f, nsteps):
+    """Advances f by nsteps steps in place, as step(); returns (status, w) with
+    w[t] the largest pressure of Eq. 15 on the wall rows y = 0 and y = ny - 1
+    of the state at the start of step t (the wall-pressure reading)."""
+    assert f.shape == (P.ny, P.nx, 9)
+    w = np.full(int(nsteps), np.nan)
+    rc = lib().oracle_step_wall_pressure(ctypes.byref(P), _ptr(f), int(nsteps), _ptr(w))
+    return rc, w
 
 
 def macros(P, f):

@@ -80,6 +80,12 @@ MUTANTS = [
     ("noise_site_index",            # noise of site (x, y) drawn with index y nx + x
      "oracle_uniform(seed, (uint64_t)i)",
      "oracle_uniform(seed, (uint64_t)((long)x * ny + y))"),
+    ("wall_pressure_row",           # the wall-pressure reading on the row next to the top wall
+     "const int rows[2] = {0, P->ny - 1};",
+     "const int rows[2] = {0, P->ny - 2};"),
+    ("wall_pressure_bottom_row",    # ... and on the row next to the bottom wall
+     "const int rows[2] = {0, P->ny - 1};",
+     "const int rows[2] = {1, P->ny - 1};"),
     ("macros_velocity_half_force",  # Eq. 6 in the reported velocity field
      "vx[i] = (jx + 0.5 * Fx[i]) / rho[i];",
      "vx[i] = jx / rho[i];"),

@@ -236,3 +236,45 @@ def test_walls_are_planes_of_mirror_symmetry(gap):
     # and the state has moved away from the start (the test is not vacuous)
     f0 = stepper.init_populations(Pw, np.tile(col[:, None], (1, nx)))
     assert np.max(np.abs(fw - f0)) > 1e-4
+
+
+def test_wall_pressure_of_a_uniform_critical_state_is_the_critical_pressure():
+    """At the critical point (rho_c, T_c) of Eq. 15, found by the multiprecision
+    solver, a uniform state at rest between walls stays uniform, and the wall
+    pressure of every step is the critical pressure p_c (0.00220840670051 for
+    a = 0.5, b = 4, R = 1)."""
+    Tc, rc, pc = coexist.critical_point()
+    P = stepper.make_params(12, 10, float(Tc), walls=True)
+    f = stepper.init_populations(P, np.full((10, 12), float(rc)))
+    rc_, w = stepper.step_wall_pressure(P, f, 6)
+    assert rc_ == 0
+    assert np.allclose(w, float(pc), rtol=1e-12, atol=0)
+    assert float(pc) == pytest.approx(0.00220840670051, rel=1e-10)
+
+
+def test_wall_pressure_reads_only_the_wall_rows_of_each_steps_start():
+    """The recorded value of step t is the largest Eq. 15 pressure on rows 0 and
+    ny - 1 of the state before step t: a denser row next to the wall does not
+    count, the densest wall row does, and the values follow the state step by
+    step."""
+    ny, nx = 16, 10
+    P = stepper.make_params(nx, ny, T07, walls=True, tau_nu=0.8)
+    rho = np.full((ny, nx), RL07)
+    rho[ny - 2, :] = RL07 * 1.05           # not a wall row
+    rho[ny - 1, 3] = RL07 * 1.02           # the densest wall site
+    rho[0, :] = RL07 * 1.01
+    f = stepper.init_populations(P, rho)
+    g = f.copy()
+    rc_, w = stepper.step_wall_pressure(P, f, 8)
+    assert rc_ == 0
+    assert w[0] == pytest.approx(stepper.eos_pressure(P, RL07 * 1.02), rel=1e-13)
+    for t in range(8):
+        d = stepper.density(P, g)
+        want = max(np.max(stepper.eos_pressure(P, d[0])), np.max(stepper.eos_pressure(P, d[-1])))
+        assert w[t] == want
+        assert stepper.step(P, g, 1) == 0
+    assert np.array_equal(f, g)
+    # the bottom wall row counts as well
+    rho[0, 5] = RL07 * 1.03
+    rc_, w = stepper.step_wall_pressure(P, stepper.init_populations(P, rho), 1)
+    assert rc_ == 0 and w[0] == pytest.approx(stepper.eos_pressure(P, RL07 * 1.03), rel=1e-13)
