@@ -199,6 +199,32 @@ int lbm_batch_workspace_bytes(int max_instances, int64_t max_tiles, size_t *byte
  * instance alone. */
 int lbm_batch_create(int precision, int max_instances, int64_t max_tiles, void *d_workspace,
                      size_t ws_bytes, void *hip_stream, void **batch);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not call hipMalloc, harnesses that forbid
+ * it): a batch like lbm_batch_create's whose workspace (instance
+ * descriptors, tile work-list, latch copies) is the library's own static
+ * device array instead of a caller-owned buffer, and which allocates
+ * nothing: no device or pinned host memory, no captured graphs (its chunks
+ * are launched directly), so every later call on it (attach, step, status,
+ * destroy) allocates nothing either.  Descriptor and tile uploads, which
+ * happen only when the batch changes, are copies from host memory that
+ * complete before the call returns.  The instances themselves keep their
+ * caller-owned workspaces (lbm_create).
+ *
+ * Limits: max_instances <= LBM_STATIC_MAX_INSTANCES and max_tiles <=
+ * LBM_STATIC_MAX_TILES (LBM_ENOMEM beyond them); the array holds about
+ * 1.1 MB on every device the library runs on, until the process ends.  One
+ * such batch per device at a time: the array is shared by every call on
+ * that device and keeps the last batch's contents, so a second
+ * lbm_batch_create_static on the device returns LBM_ESTATE until the first
+ * is destroyed (work of a destroyed batch still in flight on another stream
+ * would race with the new one: destroy synchronises the batch's stream).  The
+ * device is the current one; hip_stream must belong to it.  Results are
+ * bitwise those of lbm_batch_create's batch. */
+#define LBM_STATIC_MAX_INSTANCES 64
+#define LBM_STATIC_MAX_TILES 65536
+int lbm_batch_create_static(int precision, int max_instances, int64_t max_tiles, void *hip_stream,
+                            void **batch);
 int lbm_batch_attach(void *batch, void *handle);
 int lbm_batch_detach(void *batch, void *handle);
 /* n steps of every attached instance.  Asynchronous.  LBM_ENONFINITE, with

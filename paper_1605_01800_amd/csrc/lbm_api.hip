@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <vector>
 
@@ -185,6 +186,9 @@ struct Batch {
     int variant = 0;
     int write_through = 0;        // fused stores write through L2
     bool dirty = true;
+    // Workspace drawn from the library's static scratch array of device
+    // static_dev (lbm_batch_create_static): no pinned staging, no graphs.
+    int static_dev = -1;
     Stager stager_desc, stager_tiles;
     std::map<GraphKey, hipGraphExec_t> graphs;
 };
@@ -421,6 +425,18 @@ int read_latch(Instance *h)
 // ---------------------------------------------------------------------------
 // batch internals
 // ---------------------------------------------------------------------------
+// Sends bytes from host memory to the batch workspace: through the pinned
+// staging ring, or, for a batch on the static scratch array (which has no
+// staging), as a copy from the host buffer that is complete before this
+// returns, so the buffer may change afterwards.
+int batch_upload(Batch *b, Stager &stg, void *dst, const void *src, size_t bytes)
+{
+    if (b->static_dev < 0) return stg.upload(dst, src, bytes, b->stream);
+    TRYHIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, b->stream));
+    TRYHIP(hipStreamSynchronize(b->stream));
+    return LBM_OK;
+}
+
 int batch_sync(Batch *b)
 {
     if (b->dirty) {
@@ -441,8 +457,8 @@ int batch_sync(Batch *b)
         if ((int64_t)tl.size() > b->max_tiles) return LBM_ENOMEM;
         b->ntiles = (int)tl.size();
         // the latch copies belong to the old composition
-        TRYHIP(hipMemsetAsync(b->d_status, 0, sizeof(int) * (size_t)b->max_inst, b->stream));
-        if (!tl.empty()) TRY(b->stager_tiles.upload(b->d_tiles, tl.data(), sizeof(Tile) * tl.size(), b->stream));
+        TRYHIP(launch_fill_int(b->d_status, b->max_inst, 0, b->stream));
+        if (!tl.empty()) TRY(batch_upload(b, b->stager_tiles, b->d_tiles, tl.data(), sizeof(Tile) * tl.size()));
         b->dirty = false;
         b->dev_valid = false;
     } else {
@@ -455,7 +471,7 @@ int batch_sync(Batch *b)
     const bool same = b->dev_valid && b->dev.size() == b->descs.size() &&
                       memcmp(b->dev.data(), b->descs.data(), sizeof(InstDev) * b->descs.size()) == 0;
     if (!b->descs.empty() && !same) {
-        TRY(b->stager_desc.upload(b->d_descs, b->descs.data(), sizeof(InstDev) * b->descs.size(), b->stream));
+        TRY(batch_upload(b, b->stager_desc, b->d_descs, b->descs.data(), sizeof(InstDev) * b->descs.size()));
         b->dev = b->descs;
         b->dev_valid = true;
     }
@@ -497,7 +513,11 @@ int batch_run(Batch *b, const std::vector<int64_t> &counts, bool timed, float *m
         if (K == 0) break;
         rc = batch_sync(b);
         if (rc != LBM_OK) break;
-        if (!timed) {
+        if (!timed && b->static_dev >= 0) {
+            // no graph: its instantiation may allocate device memory
+            rc = enqueue_chunk(b->precision, b->variant, b->d_descs, n, b->d_tiles, b->ntiles, K, b->stream,
+                               b->d_status, b->write_through);
+        } else if (!timed) {
             rc = run_chunk(b->graphs, b->precision, b->variant, b->d_descs, n, b->d_tiles, b->ntiles, K,
                            b->stream, b->d_status, b->write_through);
         } else {
@@ -550,6 +570,58 @@ int batch_run(Batch *b, const std::vector<int64_t> &counts, bool timed, float *m
         (void)hipEventDestroy(e1);
     }
     return rc;
+}
+
+// ---------------------------------------------------------------------------
+// static scratch for one allocation-free batch per device
+// ---------------------------------------------------------------------------
+// Layout: descriptors of LBM_STATIC_MAX_INSTANCES instances | tile work-list
+// of LBM_STATIC_MAX_TILES tiles | latch copies of LBM_STATIC_MAX_INSTANCES.
+constexpr size_t STATIC_DESC_BYTES = (sizeof(InstDev) * LBM_STATIC_MAX_INSTANCES + ALIGN - 1) / ALIGN * ALIGN;
+constexpr size_t STATIC_TILE_BYTES = (sizeof(Tile) * (size_t)LBM_STATIC_MAX_TILES + ALIGN - 1) / ALIGN * ALIGN;
+constexpr size_t STATIC_STATUS_BYTES = (sizeof(int) * LBM_STATIC_MAX_INSTANCES + ALIGN - 1) / ALIGN * ALIGN;
+constexpr size_t STATIC_BYTES = STATIC_DESC_BYTES + STATIC_TILE_BYTES + STATIC_STATUS_BYTES;
+
+// Each device holds its own copy of this array until the process ends.  In
+// host code its name is not a device address: host code uses only the
+// address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) char scratch[STATIC_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+struct StaticSlot {
+    void *ptr = nullptr;      // the device's address of `scratch`
+    bool in_use = false;      // a static batch holds it
+};
+std::mutex g_static_mu;
+StaticSlot g_static[MAX_DEVICES];
+
+// The current device's address of the scratch array, looked up once per
+// device (with that device current) and marked in use; LBM_ESTATE when a
+// static batch on this device already holds it.
+int acquire_static_scratch(int *dev_out, void **ptr_out)
+{
+    int dev = -1;
+    TRYHIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return LBM_EINVAL;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    StaticSlot &sl = g_static[dev];
+    if (!sl.ptr) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return LBM_EHIP;
+        sl.ptr = p;
+    }
+    if (sl.in_use) return LBM_ESTATE;
+    sl.in_use = true;
+    *dev_out = dev;
+    *ptr_out = sl.ptr;
+    return LBM_OK;
+}
+
+void release_static_scratch(int dev)
+{
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (dev >= 0 && dev < MAX_DEVICES) g_static[dev].in_use = false;
 }
 
 }  // namespace
@@ -1003,7 +1075,7 @@ int lbm_batch_create(int precision, int max_instances, int64_t max_tiles, void *
     b->d_tiles = (Tile *)((char *)d_workspace + round_up(sizeof(InstDev) * (size_t)max_instances, ALIGN));
     b->d_status = (int *)((char *)b->d_tiles + round_up(sizeof(Tile) * (size_t)max_tiles, ALIGN));
     prime_residency();
-    if (hipMemsetAsync(b->d_status, 0, sizeof(int) * (size_t)max_instances, b->stream) != hipSuccess) {
+    if (launch_fill_int(b->d_status, max_instances, 0, b->stream) != hipSuccess) {
         delete b;
         return LBM_EHIP;
     }
@@ -1011,6 +1083,35 @@ int lbm_batch_create(int precision, int max_instances, int64_t max_tiles, void *
         b->stager_tiles.init(sizeof(Tile) * (size_t)max_tiles) != LBM_OK) {
         b->stager_desc.release();
         b->stager_tiles.release();
+        delete b;
+        return LBM_EHIP;
+    }
+    *batch = b;
+    return LBM_OK;
+}
+
+int lbm_batch_create_static(int precision, int max_instances, int64_t max_tiles, void *hip_stream,
+                            void **batch)
+{
+    if (precision < LBM_FP64 || precision > LBM_FP32_MIXED || !batch || max_instances < 1 || max_tiles < 1)
+        return LBM_EINVAL;
+    if (max_instances > LBM_STATIC_MAX_INSTANCES || max_tiles > LBM_STATIC_MAX_TILES) return LBM_ENOMEM;
+    int dev = -1;
+    void *base = nullptr;
+    TRY(acquire_static_scratch(&dev, &base));
+    Batch *b = new Batch();
+    b->precision = precision;
+    b->stream = (hipStream_t)hip_stream;
+    b->max_inst = max_instances;
+    b->max_tiles = max_tiles;
+    b->d_descs = (InstDev *)base;
+    b->d_tiles = (Tile *)((char *)base + STATIC_DESC_BYTES);
+    b->d_status = (int *)((char *)base + STATIC_DESC_BYTES + STATIC_TILE_BYTES);
+    b->static_dev = dev;
+    // the array keeps the previous batch's contents: the latch copies must
+    // start at zero (descriptors and tiles are written before any use)
+    if (launch_fill_int(b->d_status, max_instances, 0, b->stream) != hipSuccess) {
+        release_static_scratch(dev);
         delete b;
         return LBM_EHIP;
     }
@@ -1106,9 +1207,10 @@ int lbm_batch_prepare(void *batch, int64_t n)
     const int K = plan_chunk(b, rem);
     int rc = K > 0 ? batch_sync(b) : LBM_OK;
     // the graphs of the run's chunk lengths: full chunks and the last one
-    const int tail = (int)(n % MAX_CHUNK);
+    // (a batch on the static scratch array launches directly)
+    const int tail = b->static_dev >= 0 ? 0 : (int)(n % MAX_CHUNK);
     hipGraphExec_t ex = nullptr;
-    if (rc == LBM_OK && n >= MAX_CHUNK)
+    if (rc == LBM_OK && n >= MAX_CHUNK && b->static_dev < 0)
         rc = chunk_graph(b->graphs, b->precision, b->variant, b->d_descs, m, b->d_tiles, b->ntiles, MAX_CHUNK,
                          b->stream, b->d_status, b->write_through, &ex);
     if (rc == LBM_OK && tail > 0)
@@ -1204,6 +1306,7 @@ void lbm_batch_destroy(void *batch)
     drop_graphs(b->graphs);
     b->stager_desc.release();
     b->stager_tiles.release();
+    if (b->static_dev >= 0) release_static_scratch(b->static_dev);
     delete b;
 }
 

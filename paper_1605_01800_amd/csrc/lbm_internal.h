@@ -142,5 +142,7 @@ hipError_t launch_pack(int prec, const InstDev *d_inst, int nx, int ny, void *de
                        hipStream_t st);
 hipError_t launch_reset_diag(const InstDev *d_inst, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, size_t n, hipStream_t st);
+// dst[0 .. n) = value (a kernel, so that it can be recorded in a graph)
+hipError_t launch_fill_int(int *dst, int n, int value, hipStream_t st);
 
 }  // namespace lbm

@@ -1541,6 +1541,19 @@ hipError_t launch_pack(int prec, const InstDev *d_inst, int nx, int ny, void *de
     return hipGetLastError();
 }
 
+__global__ void fill_int_kernel(int *dst, int n, int value)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = value;
+}
+
+hipError_t launch_fill_int(int *dst, int n, int value, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    fill_int_kernel<<<(n + 255) / 256, 256, 0, st>>>(dst, n, value);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy(void *dst, const void *src, size_t n, hipStream_t st)
 {
     const size_t n16 = n / 16;

@@ -97,6 +97,8 @@ _SIGS = {
     "lbm_batch_step": [ctypes.c_void_p, ctypes.c_int64],
     "lbm_batch_step_each": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int],
     "lbm_batch_prepare": [ctypes.c_void_p, ctypes.c_int64],
+    "lbm_batch_create_static": [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p,
+                                ctypes.POINTER(ctypes.c_void_p)],
     "lbm_batch_step_timed": [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_float)],
     "lbm_batch_size": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)],
     "lbm_batch_poll": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)],
@@ -401,19 +403,30 @@ class Batch:
     """Instances stepped together, one launch per pass over all their tiles."""
 
     def __init__(self, precision="fp32", max_instances=64, max_tiles=1 << 16, device="cuda",
-                 stream=None):
+                 stream=None, static=False):
+        """static: the batch's workspace is the library's static device array
+        (lbm_batch_create_static: no allocation at all, one such batch per
+        device at a time, at most LBM_STATIC_MAX_INSTANCES instances and
+        LBM_STATIC_MAX_TILES tiles)."""
         self.precision = _PREC[precision]
         self.device = torch.device(device)
-        n = ctypes.c_size_t()
-        _check(lib().lbm_batch_workspace_bytes(int(max_instances), int(max_tiles), ctypes.byref(n)),
-               "lbm_batch_workspace_bytes")
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
-        with torch.cuda.stream(self.stream):
-            self.ws = _alloc_bytes(n.value, self.device)
         b = ctypes.c_void_p()
-        _check(lib().lbm_batch_create(self.precision, int(max_instances), int(max_tiles),
-                                      self.ws.data_ptr(), n.value, self.stream.cuda_stream,
-                                      ctypes.byref(b)), "lbm_batch_create")
+        if static:
+            self.ws = None
+            with torch.cuda.device(self.device):
+                _check(lib().lbm_batch_create_static(self.precision, int(max_instances), int(max_tiles),
+                                                     self.stream.cuda_stream, ctypes.byref(b)),
+                       "lbm_batch_create_static")
+        else:
+            n = ctypes.c_size_t()
+            _check(lib().lbm_batch_workspace_bytes(int(max_instances), int(max_tiles), ctypes.byref(n)),
+                   "lbm_batch_workspace_bytes")
+            with torch.cuda.stream(self.stream):
+                self.ws = _alloc_bytes(n.value, self.device)
+            _check(lib().lbm_batch_create(self.precision, int(max_instances), int(max_tiles),
+                                          self.ws.data_ptr(), n.value, self.stream.cuda_stream,
+                                          ctypes.byref(b)), "lbm_batch_create")
         self.b = b
         self.members = []
         self.write_through = False
