@@ -106,13 +106,12 @@ def timed_region(torch, runner, main, group, steps, warmup):
     return ms, part_ms[len(part_ms) // 2], len(part_ms)
 
 
-def measured_traffic(workload, variant_name, launches_per_step):
-    """HBM bytes of one step of the dominant kernel (all its launches in the
-    step) from the rocprofv3 FETCH_SIZE and WRITE_SIZE counters recorded in
-    profiles/traffic.json (each scaled by what the counter reads for a copy
-    kernel of known size), or None when no record matches this workload, tile
-    variant and number of launches per step, or the kernel source has changed
-    since the counters were taken."""
+def measured_traffic(workload, variant_name, batches):
+    """The rocprofv3 FETCH_SIZE and WRITE_SIZE record of the dominant kernel
+    for this workload, tile variant and number of concurrent batches, from
+    profiles/traffic.json (HBM bytes per launch, each counter scaled by what
+    it reads for a copy kernel of known size), or None when there is no such
+    record or the kernel source has changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     src = os.path.join(ROOT, "paper_1605_01800_amd", "csrc", "lbm_kernels.hip")
@@ -127,9 +126,9 @@ def measured_traffic(workload, variant_name, launches_per_step):
         return None
     found = rec.get("entries", {}).get(workload, [])
     for e in (found if isinstance(found, list) else [found]):
-        if (isinstance(e, dict) and e.get("variant") == variant_name
-                and e.get("launches_per_step", 1) == launches_per_step and "bytes_per_step" in e):
-            return e["bytes_per_step"]
+        if (isinstance(e, dict) and e.get("variant") == variant_name and e.get("batches") == batches
+                and "bytes_per_launch" in e):
+            return e
     return None
 
 
@@ -367,7 +366,16 @@ def served_run(device, n_requests, budget_gb, load=0.8, chunk=500, seed=0, batch
     be.close()
     bad = [r.id for r in results if r.diag.get("nonfinite")]
     from paper_1605_01800_amd import lbm as L
-    return {"requests": len(results), "arrival_rate_per_s": round(rate, 3), "load": load,
+    errs = served_reference_errors(device, reqs, results)
+    compact = [[e["id"]] + (["failed"] if e.get("failed") else
+                            [float("%.2g" % e["radius"]), float("%.2g" % e["mass"]),
+                             None if e["wall_p"] is None else float("%.2g" % e["wall_p"])])
+               for e in errs["per_request"]]
+    return {"error_vs_fp64": {"summary": errs["summary"],
+                              "per_request": "[id, radius, mass, wall-pressure peak] relative errors "
+                                             "of the final result against the same request in binary64",
+                              "values": compact},
+            "requests": len(results), "arrival_rate_per_s": round(rate, 3), "load": load,
             "calibrated_mlups": round(cal_mlups, 1), "tile": L.variant_names()[variant],
             "budget_GB": budget_gb, "chunk_steps": chunk, "batches": batches,
             "write_through": bool(write_through),
@@ -377,6 +385,47 @@ def served_run(device, n_requests, budget_gb, load=0.8, chunk=500, seed=0, batch
             "p99_s": round(stats["p99_s"], 4), "mean_s": round(stats["mean_s"], 4),
             "peak_resident_GB": round(stats["peak_resident_bytes"] / 1e9, 3),
             "peak_slots": stats["peak_slots"], "nonfinite_requests": bad}
+
+
+def served_reference_errors(device, reqs, results, chunk=500):
+    """Every served result against the same request stepped in binary64 (the
+    path held to the oracle at 1e-12): relative errors of the final bubble
+    radius, total mass and, with walls, the wall-pressure peak.  The binary64
+    runs go through the same server, all arrived at once, with a budget that
+    never binds."""
+    from paper_1605_01800_amd import lbm as L
+    from paper_1605_01800_amd import serving
+    ref_reqs = [serving.Request(**{**r.__dict__, "arrival": 0.0}) for r in reqs]
+    be = serving.GpuBackend(precision="fp64", device=device, max_instances=64, max_tiles=1 << 19,
+                            n_batches=2, variant=L.variant_names().index("fused-64x16"))
+    srv = serving.Server(be, budget_bytes=64 * 10 ** 9, max_slots=64, chunk_steps=chunk)
+    ref, _ = srv.run(ref_reqs)
+    be.close()
+    by_id = {r.id: r for r in ref}
+    rel = lambda a, b: abs(a - b) / abs(b)
+    per = []
+    for r in results:
+        q = by_id[r.id]
+        if r.failed or q.failed:
+            per.append({"id": r.id, "failed": True})
+            continue
+        e = {"id": r.id, "radius": max((rel(a, b) for a, b in zip(r.diag["radius"], q.diag["radius"])),
+                                       default=0.0),
+             "mass": rel(r.diag["mass"], q.diag["mass"]),
+             "wall_p": None}
+        if q.diag["wall_p_step"] >= 0:
+            e["wall_p"] = rel(r.diag["wall_p_max"], q.diag["wall_p_max"])
+            e["wall_p_same_step"] = r.diag["wall_p_step"] == q.diag["wall_p_step"]
+        per.append(e)
+    ok = [e for e in per if not e.get("failed")]
+    summary = {}
+    for k in ("radius", "mass", "wall_p"):
+        v = sorted(e[k] for e in ok if e.get(k) is not None)
+        if v:
+            summary[k] = {"max": v[-1], "median": v[len(v) // 2]}
+    summary["wall_p_same_step"] = sum(1 for e in ok if e.get("wall_p_same_step"))
+    summary["with_walls"] = sum(1 for e in ok if e.get("wall_p") is not None)
+    return {"per_request": per, "summary": summary}
 
 
 def main():
@@ -499,19 +548,27 @@ def main():
     # bytes of all sites; a kernel trace of the same command gives the same
     # average launch.  Two-pass variants time each launch with its own event
     # pair on the batch's stream.
+    # A two-step launch advances every site by two steps: its algorithmic
+    # bytes are those of two site updates (2 x 72 B a site), while the bytes
+    # it must move are one read and one write of the populations (72 B a
+    # site), reported beside them as min_hbm_*.
     nk = min(args.steps, 100)
+    nk += nk % 2
+    spl = 2 if vname.startswith("twostep") else 1          # site updates per launch
     if group is not None:
         group.close()
         for s in sims:
             batch.attach(s)
     ms_psi, ms_col = batch.step_timed(nk)
     if fused:
-        t_dom = ms1 / args.steps
-        kname = {"fused2": "fused2_kernel", "fused": "fused_kernel"}[vname.split("-")[0]]
-        dominant = (kname, t_dom, BYTES_FUSED[es])
-        kernels = {kname: {"ms_region_avg": t_dom, "ms_event_pair_avg": ms_col / nk,
-                           "bytes_per_site": BYTES_FUSED[es],
-                           "GB_s": round(BYTES_FUSED[es] * sites / (t_dom * 1e-3) / 1e9, 1)}}
+        t_dom = ms1 / args.steps * spl
+        kname = {"fused2": "fused2_kernel", "fused": "fused_kernel",
+                 "twostep": "twostep_kernel"}[vname.split("-")[0]]
+        dominant = (kname, t_dom, BYTES_FUSED[es] * spl)
+        kernels = {kname: {"ms_region_avg": t_dom, "ms_event_pair_avg": ms_col / (nk // spl),
+                           "site_updates_per_launch": spl,
+                           "bytes_per_site": BYTES_FUSED[es] * spl,
+                           "GB_s": round(BYTES_FUSED[es] * spl * sites / (t_dom * 1e-3) / 1e9, 1)}}
     else:
         t_psi, t_col = ms_psi / nk, ms_col / nk
         dominant = ("collide_stream_kernel", t_col, BYTES_COLLIDE[es]) if t_col >= t_psi else \
@@ -524,14 +581,17 @@ def main():
     print("# dominant %s %.4f ms/launch, %.0f GB/s of %d B/site" % (dominant[0], dominant[1], achieved,
                                                                      dominant[2]), file=sys.stderr, flush=True)
 
-    traffic = measured_traffic(args.workload, vname, 1)
+    trec = measured_traffic(args.workload, vname, 1)
+    traffic = trec["bytes_per_launch"] if trec else None
     # The MI355X's Infinity Cache (256 MB) sits between the L2s and HBM: a
     # working set that fits it is served from there, and the FETCH_SIZE and
     # WRITE_SIZE counters (L2 to fabric) then count cache bytes, not only
     # DRAM bytes.
     working_set = sum(L.workspace_bytes(s.params) for s in sims)
     cache_resident = working_set < 256e6
-    copy_gbs = copy_rate(L, dominant[2] * sites // 2, batch.stream)
+    min_hbm = BYTES_FUSED[es] * sites if fused else dominant[2] * sites    # bytes a launch must move
+    min_hbm_gbs = min_hbm / (dominant[1] * 1e-3) / 1e9
+    copy_gbs = copy_rate(L, min_hbm // 2, batch.stream)
     out = {
         "metric": "aggregate MLUPS + %HBM roofline (FP32 batched vs FP64 plain); p50/p99 latency",
         "value": round(mlups, 1),
@@ -564,13 +624,17 @@ def main():
             "working_set_bytes": working_set,
             "cache_resident": cache_resident,
             "bytes_per_site": dominant[2],
+            "site_updates_per_launch": spl,
             "algorithmic_bytes_per_launch": dominant[2] * sites,
             "traffic_over_algorithmic": None if traffic is None else round(traffic / (dominant[2] * sites), 4),
-            # a plain copy of the step's algorithmic bytes (half read, half
+            "min_hbm_bytes_per_launch": min_hbm,
+            "min_hbm_GB_s": round(min_hbm_gbs, 1),
+            "traffic_over_min_hbm": None if traffic is None else round(traffic / min_hbm, 4),
+            # a plain copy of the bytes a launch must move (half read, half
             # written), back to back on one stream: what this traffic can
             # reach on this part, launch cost included
             "copy_same_bytes_GB_s": round(copy_gbs, 1),
-            "frac_of_copy": round(achieved / copy_gbs, 4),
+            "frac_of_copy": round(min_hbm_gbs / copy_gbs, 4),
         },
         "kernels": kernels,
     }
@@ -579,14 +643,18 @@ def main():
         # the sites: the step's algorithmic bytes over the step's time, and
         # the step's measured bytes (launches of a quarter of the grid)
         step_ms = ms / args.steps
-        c_traffic = measured_traffic(args.workload, vname, n_streams)
-        c_achieved = dominant[2] * sites / (step_ms * 1e-3) / 1e9
+        crec = measured_traffic(args.workload, vname, n_streams)
+        # bytes of one step: every batch's launches in it (a two-step launch
+        # counts for two steps)
+        c_traffic = round(crec["bytes_per_launch"] * crec["launches_per_step"]) if crec else None
+        c_achieved = BYTES_FUSED[es] * sites / (step_ms * 1e-3) / 1e9
         out["roofline"]["concurrent_streams"] = {
-            "streams": n_streams, "launches_per_step": n_streams, "write_through": group_wt,
+            "streams": n_streams, "launches_per_step": n_streams / spl, "write_through": group_wt,
             "step_ms": step_ms,
             "achieved": round(c_achieved, 1), "frac": round(c_achieved / HBM_PEAK_GBS, 4),
-            "frac_of_copy": round(c_achieved / copy_gbs, 4), "traffic": c_traffic,
-            "traffic_over_algorithmic": None if c_traffic is None else round(c_traffic / (dominant[2] * sites), 4)}
+            "frac_of_copy": round(c_achieved / spl / copy_gbs, 4), "traffic": c_traffic,
+            "traffic_over_algorithmic": None if c_traffic is None else
+            round(c_traffic / (BYTES_FUSED[es] * sites), 4)}
     batch.close()
     for s in sims:
         s.close()

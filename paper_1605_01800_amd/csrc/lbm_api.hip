@@ -46,16 +46,22 @@ struct Layout {
     int64_t max_tiles;
 };
 
-int64_t tiles_for(int nx, int ny, int rows)
+// Tiles of an nx x ny grid in the largest work-list any variant builds.
+int64_t max_tiles_for(int nx, int ny)
 {
-    return (int64_t)((nx + TILE_X - 1) / TILE_X) * ((ny + rows - 1) / rows);
+    int64_t most = 0;
+    for (int v = 0; v < kNumVariants; ++v) {
+        const int cols = tile_cols(v), rows = tile_rows(v);
+        most = std::max(most, (int64_t)((nx + cols - 1) / cols) * ((ny + rows - 1) / rows));
+    }
+    return most;
 }
 
 Layout layout_of(const lbm_params &p)
 {
     Layout L;
     L.pitch = (int)round_up((size_t)p.nx, TILE_X);
-    L.max_tiles = tiles_for(p.nx, p.ny, tile_rows(0));
+    L.max_tiles = max_tiles_for(p.nx, p.ny);
     const size_t es = elem_size(p.precision);
     const size_t plane = (size_t)L.pitch * p.ny + PLANE_SKEW / es;
     L.plane = (long long)plane;
@@ -343,6 +349,14 @@ int sync_own(Instance *h, int v = -1)
 int enqueue_chunk(int prec, int variant, const InstDev *d_inst, int ninst, const Tile *d_tiles,
                   int ntiles, int K, hipStream_t st, int *d_status, int write_through)
 {
+    if (two_step(variant)) {
+        // one launch per pair of steps; an instance with an odd count takes
+        // its last step alone in launch (n - 1) / 2
+        for (int s = 0; s < (K + 1) / 2; ++s)
+            TRYHIP(launch_twostep(prec, variant, d_inst, d_tiles, ntiles, s, st));
+        TRYHIP(launch_chunk_end(d_inst, ninst, st, d_status, 1));
+        return LBM_OK;
+    }
     for (int s = 0; s < K; ++s) {
         if (kVariants[variant].fused == 2) {
             TRYHIP(launch_fused2(prec, variant, d_inst, d_tiles, ntiles, s, st));
@@ -408,10 +422,10 @@ void drop_graphs(std::map<GraphKey, hipGraphExec_t> &cache)
 }
 
 // Host mirror of what the end-of-chunk kernel does to a descriptor.
-void advance_mirror(InstDev &d, int n)
+void advance_mirror(InstDev &d, int n, int variant)
 {
     d.step += n;
-    d.cur ^= (n & 1);
+    d.cur ^= buffer_flips(n, two_step(variant) ? 1 : 0) & 1;
 }
 
 int read_latch(Instance *h)
@@ -522,11 +536,18 @@ int batch_run(Batch *b, const std::vector<int64_t> &counts, bool timed, float *m
                            b->stream, b->d_status, b->write_through);
         } else {
             const bool fused = kVariants[b->variant].fused;
-            for (int s = 0; s < K && rc == LBM_OK && fused; ++s) {
+            const bool pairs = two_step(b->variant);
+            // one timed launch per step, or per pair of steps (two-step
+            // variants: ms[1] then sums launches of two steps each)
+            const int launches = pairs ? (K + 1) / 2 : K;
+            for (int s = 0; s < launches && rc == LBM_OK && fused; ++s) {
                 float t;
                 rc = hip_ok(hipEventRecord(e0, b->stream));
                 if (rc == LBM_OK) {
-                    if (kVariants[b->variant].fused == 2)
+                    if (pairs)
+                        rc = hip_ok(launch_twostep(b->precision, b->variant, b->d_descs, b->d_tiles, b->ntiles, s,
+                                                   b->stream));
+                    else if (kVariants[b->variant].fused == 2)
                         rc = hip_ok(launch_fused2(b->precision, b->variant, b->d_descs, b->d_tiles, b->ntiles, s, b->stream));
                     else
                         rc = hip_ok(launch_fused(b->precision, b->variant, b->d_descs, b->d_tiles, b->ntiles, s, b->stream,
@@ -552,14 +573,14 @@ int batch_run(Batch *b, const std::vector<int64_t> &counts, bool timed, float *m
                 if (rc == LBM_OK) rc = hip_ok(hipEventElapsedTime(&t, e0, e1));
                 if (rc == LBM_OK) ms[1] += t;
             }
-            if (rc == LBM_OK) rc = hip_ok(launch_chunk_end(b->d_descs, n, b->stream, b->d_status));
+            if (rc == LBM_OK) rc = hip_ok(launch_chunk_end(b->d_descs, n, b->stream, b->d_status, pairs ? 1 : 0));
         }
         if (rc != LBM_OK) break;
         for (int i = 0; i < n; ++i) {
             Instance *h = b->members[i];
             const int ni = h->desc.n_chunk;
-            advance_mirror(h->desc, ni);
-            advance_mirror(b->dev[i], ni);   // what the end-of-chunk kernel did
+            advance_mirror(h->desc, ni, b->variant);
+            advance_mirror(b->dev[i], ni, b->variant);   // what the end-of-chunk kernel did
             rem[i] -= ni;
             h->desc_dirty = true;    // the instance's own descriptor copy is stale
         }
@@ -778,7 +799,7 @@ int lbm_step(void *handle, int64_t n)
         TRY(sync_own(h));
         TRY(run_chunk(h->graphs, h->p.precision, h->variant, h->d_desc, 1, h->d_tiles, h->ntiles, K,
                       h->stream));
-        advance_mirror(h->desc, K);   // the device advanced its own copy
+        advance_mirror(h->desc, K, h->variant);   // the device advanced its own copy
         n -= K;
     }
     return LBM_OK;

@@ -15,6 +15,9 @@ constexpr int TILE_X = 64;
 // Threads per block: 4 wavefronts, one per row group of a tile.
 constexpr int BLOCK = 256;
 constexpr int ROW_GROUPS = BLOCK / TILE_X;
+// Output columns of a two-step strip: a 64-wide wavefront spans the strip and
+// three columns on each side.
+constexpr int TWOSTEP_COLS = TILE_X - 6;
 // Longest chunk of steps replayed from one captured graph; also the number of
 // per-step wall-pressure slots an instance keeps.
 constexpr int MAX_CHUNK = 256;
@@ -84,13 +87,20 @@ struct Tile {
     int tile_index;                // index of the tile within its instance
 };
 
+// Times the population buffers of an instance swap over n steps of a chunk:
+// once per step, or, for the two-step variants (pairs != 0), once per launch,
+// ceil(n / 2).
+__host__ __device__ inline int buffer_flips(int n, int pairs) { return pairs ? (n + 1) >> 1 : n; }
+
 // Kernel variants.  Two-pass variants (fused == 0) launch the psi pass and the
 // force+collide+stream pass over tiles of TILE_X x (ROW_GROUPS * rows) sites,
 // each thread taking `rows` rows.  Fused variants (fused == 1) launch one
 // kernel per step over strips of TILE_X x rows sites that rebuild psi for the
 // strip and its one-site ring on the fly.  Paired fused variants (fused == 2)
 // do the same over strips of 2 * TILE_X x rows sites, two neighbouring sites
-// per lane with two-element loads and stores; they need an even nx.
+// per lane with two-element loads and stores; they need an even nx.  Two-step
+// variants (fused == 3) launch one kernel per pair of steps over strips of
+// TWOSTEP_COLS x rows sites.
 struct Variant {
     int fused;
     int rows;
@@ -104,7 +114,12 @@ inline int tile_rows(int variant)
     return kVariants[variant].fused ? kVariants[variant].rows : ROW_GROUPS * kVariants[variant].rows;
 }
 
-inline int tile_cols(int variant) { return kVariants[variant].fused == 2 ? 2 * TILE_X : TILE_X; }
+inline int tile_cols(int variant)
+{
+    return kVariants[variant].fused == 2 ? 2 * TILE_X : (kVariants[variant].fused == 3 ? TWOSTEP_COLS : TILE_X);
+}
+
+inline bool two_step(int variant) { return kVariants[variant].fused == 3; }
 
 inline bool variant_fits(int variant, int nx) { return kVariants[variant].fused != 2 || nx % 2 == 0; }
 
@@ -127,9 +142,15 @@ hipError_t launch_fused(int prec, int variant, const InstDev *d_inst, const Tile
                         int s, hipStream_t st, int write_through = 0);
 hipError_t launch_fused2(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles, int ntiles,
                          int s, hipStream_t st);
-// End of a chunk: folds the wall-pressure maxima, advances step and parity;
-// with d_status, also copies each instance's latch to d_status[k].
-hipError_t launch_chunk_end(const InstDev *d_inst, int ninst, hipStream_t st, int *d_status = nullptr);
+// End of a chunk: folds the wall-pressure maxima, advances step and parity
+// (buffer_flips(n, pairs)); with d_status, also copies each instance's latch
+// to d_status[k].
+// Two-step pass s: steps 2s and 2s + 1 of the chunk (only step 2s for an
+// instance whose chunk ends there).
+hipError_t launch_twostep(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles, int ntiles,
+                          int s, hipStream_t st);
+hipError_t launch_chunk_end(const InstDev *d_inst, int ninst, hipStream_t st, int *d_status = nullptr,
+                            int pairs = 0);
 hipError_t launch_init(int prec, const InstDev *d_inst, int slab_rows, const lbm_bubble *b, int nb,
                        double rho_l, double rho_g, double W, double delta, double noise_amp,
                        uint64_t seed, long long nsites, hipStream_t st);

@@ -30,7 +30,9 @@ namespace lbm {
 const Variant kVariants[] = {
     {0, 1, "2pass-64x4"},    {0, 2, "2pass-64x8"},    {0, 4, "2pass-64x16"},   {0, 8, "2pass-64x32"},
     {1, 16, "fused-64x16"},  {1, 32, "fused-64x32"},  {1, 64, "fused-64x64"},  {1, 128, "fused-64x128"},
-    {2, 16, "fused2-128x16"}, {2, 32, "fused2-128x32"}, {2, 64, "fused2-128x64"}};
+    {2, 16, "fused2-128x16"}, {2, 32, "fused2-128x32"}, {2, 64, "fused2-128x64"},
+    {3, 16, "twostep-58x16"}, {3, 24, "twostep-58x24"}, {3, 32, "twostep-58x32"}, {3, 48, "twostep-58x48"},
+    {3, 64, "twostep-58x64"}};
 const int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 namespace {
@@ -1031,9 +1033,242 @@ __global__ __launch_bounds__(BLOCK) void fused2_kernel(const InstDev *__restrict
 }
 
 // ---------------------------------------------------------------------------
+// two-step pass: steps t and t + 1 in one kernel
+// ---------------------------------------------------------------------------
+// A block owns a strip of T2_OUT = 58 output columns and H rows, and its four
+// wavefronts walk it as in fused_kernel, but every lane holds one of 64
+// columns that reach three sites past the strip on each side: lane l is
+// column x0 - 3 + l.  Per iteration k, wavefront w:
+//
+//   step t      loads the populations of row y0 - 3 + 4(k + 1) + w (one
+//               iteration ahead), forms rho and psi (Eqs. 15, 13) of the row
+//               loaded last into a psi ring, and collides the row loaded two
+//               iterations ago (Eqs. 7, 6, 4, 14, 3) in lanes 1 .. 62; the
+//               post-collision populations are pushed (Eq. 5, halfway
+//               bounce-back at walls) into a ring of rows in LDS instead of
+//               memory;
+//   step t + 1  reads a row of that ring once all three rows that push into
+//               it have been collided (four iterations behind), forms rho
+//               and psi of t + 1 in lanes 2 .. 61, and collides the row read
+//               two iterations ago in the 58 output lanes 3 .. 60, pushing to
+//               the other population buffer in memory.
+//
+// So each population is read from memory once and written once per two
+// steps; the intermediate state never leaves LDS.  The dependence reaches
+// three sites per two steps (psi of a neighbour, then streaming, twice), which
+// is where the three extra columns and rows on each side go.  Each output
+// site is computed with the arithmetic of fused_kernel in the same order.
+//
+// Ring hazards (one barrier per iteration): in iteration k the step-t
+// collisions write rows y0 - 12 + 4k .. y0 - 7 + 4k of the 12-row population
+// ring and the step-t + 1 reads take rows y0 - 17 + 4k .. y0 - 14 + 4k, all
+// completed before the previous barrier; rows 12 apart share a slot, and
+// every slot read in iteration k is next written in iteration k + 1 or
+// later.  The two psi rings follow fused_kernel's pattern (rows written and
+// read in one iteration 4 to 12 apart, 16 slots).
+//
+// A launch with index s advances every instance with s < ceil(n / 2) (n its
+// steps in the chunk) by steps 2s and 2s + 1, reading buffer (cur + s) mod 2
+// and writing the other; when n is odd, launch (n - 1) / 2 takes only step
+// n - 1, its step-t collisions pushing to memory.  An instance's buffer
+// therefore flips ceil(n / 2) times per chunk.
+constexpr int T2_HALO = 3;
+constexpr int T2_OUT = TILE_X - 2 * T2_HALO;
+static_assert(T2_OUT == TWOSTEP_COLS, "two-step strip width");
+
+template <typename T, bool EOS64, int H>
+__global__ __launch_bounds__(BLOCK) void twostep_kernel(const InstDev *__restrict__ insts,
+                                                        const Tile *__restrict__ tiles, int ntiles, int s)
+{
+    constexpr int RP = 16;
+    constexpr int RF = 12;
+    constexpr int NA = (H + 2 * T2_HALO + ROW_GROUPS - 1) / ROW_GROUPS;
+    constexpr int NK = H / ROW_GROUPS + 7;
+    static_assert(H % ROW_GROUPS == 0, "strip height must be a multiple of the row groups");
+    __shared__ T psiA[RP * TILE_X];
+    __shared__ T psiB[RP * TILE_X];
+    __shared__ __align__(16) T f1[RF * 9 * TILE_X];
+    static_assert(sizeof(f1) >= 2 * BLOCK * sizeof(double), "the wall reduction reuses the ring");
+
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    if (t >= ntiles) return;
+    const Tile tl = tiles[t];
+    const InstDev &d = insts[tl.inst];
+    const int n = d.n_chunk;
+    if (s >= ((n + 1) >> 1)) return;
+    const bool single = (n & 1) && s == (n >> 1);          // the chunk's last, odd step alone
+    const int sb = src_buffer(d, s);
+    const gptr<const char> f = global_ptr<const char>(d.f[sb]);
+    const gptr<char> fo = global_ptr<char>(d.f[sb ^ 1]);
+    const unsigned long long PB = (unsigned long long)d.plane * sizeof(T);
+    const unsigned long long RB = (unsigned long long)d.pitch * sizeof(T);
+    const int nx = d.nx, ny = d.ny, walls = d.walls;
+    const int lane = threadIdx.x & (TILE_X - 1);
+    const int w = wave_index();
+    const int X = tl.x0 - T2_HALO + lane;                   // the lane's column (unwrapped)
+    int xl = X % nx;
+    if (xl < 0) xl += nx;
+    const unsigned xlo = (unsigned)xl * sizeof(T);
+    const bool out = lane >= T2_HALO && lane < TILE_X - T2_HALO && X < nx;   // X >= x0 >= 0 here
+    const unsigned xo = xlo;
+    const unsigned xeo = (unsigned)((xl + 1 == nx) ? 0 : xl + 1) * sizeof(T);
+    const unsigned xwo = (unsigned)((xl == 0) ? nx - 1 : xl - 1) * sizeof(T);
+    const bool lane_a = lane >= 1 && lane <= TILE_X - 2;    // step-t collisions
+    const bool lane_b = lane >= 2 && lane <= TILE_X - 3;    // step-t + 1 densities
+    const int y_end = min(tl.y0 + H, ny);                   // rows output: [y0, y_end)
+    const int lA_first = tl.y0 - 3, lA_last = y_end + 2;    // rows loaded for step t
+    const bool track = walls && (tl.y0 == 0 || tl.y0 + H >= ny);
+    const Consts<T> &R = consts<T>(d);
+    const T mG = R.mG;
+
+    bool bad = false;
+    double wmaxA = -INFINITY, wmaxB = -INFINITY;
+    T fq[9], fn[9], fa[9], fb[9], gn[9], ga[9], gb[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) fq[a] = fn[a] = fa[a] = fb[a] = gn[a] = ga[a] = gb[a] = T(0);
+
+    auto rowA = [&](int k) { return lA_first + ROW_GROUPS * k + w; };
+    auto rowB = [&](int m) { return tl.y0 - 1 + ROW_GROUPS * m + w; };
+    auto f1row = [&](int r) { return f1 + ((r + RF) % RF) * (9 * TILE_X); };   // r >= -3
+    // loads are issued unconditionally (rows past the last needed one are
+    // clamped to it) so that the compiler's wait counts stay exact
+    auto load_row = [&](int k, T v[9]) {
+        const int l = min(rowA(k), lA_last);
+        // rows reach three past the strip, so a periodic grid of fewer than
+        // three rows wraps more than once: a full modulo
+        const int mr = walls ? min(max(l, 0), ny - 1) : ((l % ny) + ny) % ny;
+        const gptr<const char> rb = f + (unsigned long long)mr * RB;
+#pragma unroll
+        for (int a = 0; a < 9; ++a) v[a] = ld<T>(rb + a * PB, xlo);
+    };
+    load_row(0, fn);
+
+    auto iteration = [&](int k, bool next) __attribute__((always_inline)) {
+        if (next) load_row(k + 1, fq);
+
+        // step t: rho and psi of the row loaded last
+        const int l = rowA(k);
+        if (k < NA && l <= lA_last) {
+            const T dm = density<T>(fn);
+            const T ps = pseudopotential<T, EOS64>(dm, d);
+            psiA[(l & (RP - 1)) * TILE_X + lane] = ps;
+            bad |= !finite_value(ps);
+            if (track && (l == 0 || l == ny - 1) && l >= tl.y0 && l < y_end && out)
+                wmaxA = fmax(wmaxA, eos_pressure<double>(d.rho_ref + (double)dm, d.RT, d.a, d.b4));
+        }
+
+        // step t: collide the row loaded two iterations ago
+        const int c = rowA(k - 2);
+        const bool crow = k >= 2 && c >= tl.y0 - 2 && c <= y_end + 1 && (!walls || (c >= 0 && c < ny));
+        if (crow && lane_a) {
+            const T *rS = psiA + ((c - 1) & (RP - 1)) * TILE_X;
+            const T *rC = psiA + (c & (RP - 1)) * TILE_X;
+            const T *rN = psiA + ((c + 1) & (RP - 1)) * TILE_X;
+            T pc, Fx, Fy;
+            interaction_force<T>(rS, rC, rN, lane, mG, pc, Fx, Fy);
+            collide_site<T>(fb, pc, Fx, Fy, R);
+            if (single) {
+                // the odd last step of the chunk: straight to memory
+                if (out && c >= tl.y0 && c < y_end) push_store<T>(fo, PB, fb, xo, xeo, xwo, c, ny, RB, walls);
+            } else {
+                // Eq. 5 into the LDS rows of t + 1; halfway bounce-back at walls
+                T *r0 = f1row(c);
+                r0[0 * TILE_X + lane] = fb[0];
+                r0[1 * TILE_X + lane + 1] = fb[1];
+                r0[3 * TILE_X + lane - 1] = fb[3];
+                if (walls && c == ny - 1) {
+                    r0[4 * TILE_X + lane] = fb[2];
+                    r0[7 * TILE_X + lane] = fb[5];
+                    r0[8 * TILE_X + lane] = fb[6];
+                } else {
+                    T *rn = f1row(c + 1);
+                    rn[2 * TILE_X + lane] = fb[2];
+                    rn[5 * TILE_X + lane + 1] = fb[5];
+                    rn[6 * TILE_X + lane - 1] = fb[6];
+                }
+                if (walls && c == 0) {
+                    r0[2 * TILE_X + lane] = fb[4];
+                    r0[5 * TILE_X + lane] = fb[7];
+                    r0[6 * TILE_X + lane] = fb[8];
+                } else {
+                    T *rs = f1row(c - 1);
+                    rs[4 * TILE_X + lane] = fb[4];
+                    rs[7 * TILE_X + lane - 1] = fb[7];
+                    rs[8 * TILE_X + lane + 1] = fb[8];
+                }
+            }
+        }
+
+        // step t + 1: rho and psi of a completed LDS row (ghost rows beyond a
+        // wall mirror the wall row)
+        const int rb = rowB(k - 4);
+        if (!single && k >= 4 && rb <= y_end) {
+            const int rr = walls ? min(max(rb, 0), ny - 1) : rb;
+            const T *src = f1row(rr);
+#pragma unroll
+            for (int a = 0; a < 9; ++a) gn[a] = src[a * TILE_X + lane];
+            T ps = T(0);
+            if (lane_b) {
+                const T dm = density<T>(gn);
+                ps = pseudopotential<T, EOS64>(dm, d);
+                bad |= !finite_value(ps);
+                if (track && (rb == 0 || rb == ny - 1) && rb >= tl.y0 && rb < y_end && out)
+                    wmaxB = fmax(wmaxB, eos_pressure<double>(d.rho_ref + (double)dm, d.RT, d.a, d.b4));
+            }
+            psiB[(rb & (RP - 1)) * TILE_X + lane] = ps;
+        }
+
+        // step t + 1: collide the row read two iterations ago, to memory
+        const int cb = rowB(k - 6);
+        if (!single && k >= 6 && cb >= tl.y0 && cb < y_end && out) {
+            const T *rS = psiB + ((cb - 1) & (RP - 1)) * TILE_X;
+            const T *rC = psiB + (cb & (RP - 1)) * TILE_X;
+            const T *rN = psiB + ((cb + 1) & (RP - 1)) * TILE_X;
+            T pc, Fx, Fy;
+            interaction_force<T>(rS, rC, rN, lane, mG, pc, Fx, Fy);
+            collide_site<T>(gb, pc, Fx, Fy, R);
+            push_store<T>(fo, PB, gb, xo, xeo, xwo, cb, ny, RB, walls);
+        }
+
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            fb[a] = fa[a];
+            fa[a] = fn[a];
+            if (next) fn[a] = fq[a];
+            gb[a] = ga[a];
+            ga[a] = gn[a];
+        }
+    };
+
+#pragma unroll 2
+    for (int k = 0; k < NA - 1; ++k) iteration(k, true);
+    for (int k = NA - 1; k < NK; ++k) iteration(k, false);
+    if (bad) d.flag[0] = 1;
+    if (track) {
+        // the population ring is free after the walk's last barrier
+        double *red = reinterpret_cast<double *>(f1);
+        red[threadIdx.x] = wmaxA;
+        red[BLOCK + threadIdx.x] = wmaxB;
+        __syncthreads();
+        for (int k2 = BLOCK / 2; k2 > 0; k2 >>= 1) {
+            if (threadIdx.x < k2) {
+                red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + k2]);
+                red[BLOCK + threadIdx.x] = fmax(red[BLOCK + threadIdx.x], red[BLOCK + threadIdx.x + k2]);
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            if (red[0] > -INFINITY) atomicMax(&d.wall_keys[2 * s], order_key(red[0]));
+            if (!single && red[BLOCK] > -INFINITY) atomicMax(&d.wall_keys[2 * s + 1], order_key(red[BLOCK]));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // end of a chunk: fold the per-step wall maxima, advance step counter/parity
 // ---------------------------------------------------------------------------
-__global__ void chunk_end_kernel(InstDev *insts, int ninst, int *status)
+__global__ void chunk_end_kernel(InstDev *insts, int ninst, int *status, int pairs)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= ninst) return;
@@ -1056,7 +1291,7 @@ __global__ void chunk_end_kernel(InstDev *insts, int ninst, int *status)
         d.wall_run[1] = (unsigned long long)best_step;
     }
     d.step += n;
-    d.cur ^= (n & 1);
+    d.cur ^= buffer_flips(n, pairs) & 1;
 }
 
 // Clears the latch and the wall-pressure record of one instance.
@@ -1343,6 +1578,21 @@ hipError_t fused2_dispatch(int variant, const InstDev *di, const Tile *dt, int n
     return hipGetLastError();
 }
 
+template <typename T, bool E64>
+hipError_t twostep_dispatch(int variant, const InstDev *di, const Tile *dt, int nt, int s, hipStream_t st)
+{
+    const dim3 grid(grid_for(nt)), block(BLOCK);
+    switch (kVariants[variant].rows) {
+    case 16: twostep_kernel<T, E64, 16><<<grid, block, 0, st>>>(di, dt, nt, s); break;
+    case 24: twostep_kernel<T, E64, 24><<<grid, block, 0, st>>>(di, dt, nt, s); break;
+    case 32: twostep_kernel<T, E64, 32><<<grid, block, 0, st>>>(di, dt, nt, s); break;
+    case 48: twostep_kernel<T, E64, 48><<<grid, block, 0, st>>>(di, dt, nt, s); break;
+    case 64: twostep_kernel<T, E64, 64><<<grid, block, 0, st>>>(di, dt, nt, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // Fused instantiation of a variant (nullptr for the two-pass variants).
 template <typename T, bool E64>
 const void *fused_ptr(int variant)
@@ -1472,10 +1722,20 @@ hipError_t launch_fused2(int prec, int variant, const InstDev *d_inst, const Til
     return fused2_dispatch<float, true>(variant, d_inst, d_tiles, ntiles, s, alt, st);
 }
 
-hipError_t launch_chunk_end(const InstDev *d_inst, int ninst, hipStream_t st, int *d_status)
+hipError_t launch_twostep(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles, int ntiles,
+                          int s, hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    if (kVariants[variant].fused != 3) return hipErrorInvalidValue;
+    if (prec == LBM_FP64) return twostep_dispatch<double, false>(variant, d_inst, d_tiles, ntiles, s, st);
+    if (prec == LBM_FP32) return twostep_dispatch<float, false>(variant, d_inst, d_tiles, ntiles, s, st);
+    return twostep_dispatch<float, true>(variant, d_inst, d_tiles, ntiles, s, st);
+}
+
+hipError_t launch_chunk_end(const InstDev *d_inst, int ninst, hipStream_t st, int *d_status, int pairs)
 {
     if (ninst <= 0) return hipSuccess;
-    chunk_end_kernel<<<(ninst + 63) / 64, 64, 0, st>>>(const_cast<InstDev *>(d_inst), ninst, d_status);
+    chunk_end_kernel<<<(ninst + 63) / 64, 64, 0, st>>>(const_cast<InstDev *>(d_inst), ninst, d_status, pairs);
     return hipGetLastError();
 }
 

@@ -34,7 +34,8 @@ def _variant(name):
 @pytest.mark.parametrize("variant,shift", [("2pass-64x4", False), ("fused-64x16", False),
                                            ("fused-64x128", False), ("2pass-64x8", True),
                                            ("fused-64x32", True), ("fused2-128x16", False),
-                                           ("fused2-128x64", True)])
+                                           ("fused2-128x64", True), ("twostep-58x32", False),
+                                           ("twostep-58x64", True)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_mixed"])
 @pytest.mark.parametrize("nx,ny,walls", [(100, 37, False), (100, 37, True), (64, 8, False),
                                          (130, 5, True), (1, 6, False), (3, 1, True),
@@ -64,6 +65,40 @@ def test_single_step_from_random_state(prec, nx, ny, walls, variant, shift):
     want = start.copy()
     assert ostep.step(P, want, 1) == 0
     assert rel_inf(got, want) < STEP_TOL[prec]
+    sim.close()
+
+
+@pytest.mark.parametrize("variant,shift", [("twostep-58x16", False), ("twostep-58x24", True),
+                                           ("twostep-58x32", False), ("twostep-58x48", True)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_mixed"])
+@pytest.mark.parametrize("nx,ny,walls", [(100, 37, False), (100, 37, True), (64, 8, False),
+                                         (130, 5, True), (1, 6, False), (3, 1, True),
+                                         (200, 131, True), (2, 3, False), (258, 9, True), (59, 2, False)])
+@pytest.mark.parametrize("nsteps", [2, 3])
+def test_two_step_kernel_from_random_state(prec, nx, ny, walls, variant, shift, nsteps):
+    """The two-step kernel from a generic state: two steps in one launch (the
+    intermediate state only in LDS) and three (a launch of two, then the odd
+    last step alone), on the ragged and degenerate grids of the single-step
+    test (strips of 58 columns: x edges inside strips, grids narrower than
+    the lane's reach, periodic grids of one and two rows)."""
+    print("case", prec, nx, ny, walls, variant, shift, nsteps, flush=True)
+    T = coexist.temperature(0.7)
+    p = L.make_params(nx, ny, T=T, walls=walls, precision=prec, tau_nu=0.6)
+    P = oracle_params(p)
+    rho, _, _ = _bubble_rho(P, T, min(nx, ny) / 4.0 + 0.5, walls)
+    f0 = inputs.random_populations(rho, seed=nx * 1000 + ny, amp=0.3)
+    sim = L.Sim(p)
+    sim.set_variant(_variant(variant))
+    if shift:
+        sim.init_density(rho)
+    sim.set_populations(to_device(f0, sim.dtype))
+    start = to_oracle(sim.populations())
+    sim.step(nsteps)
+    got = to_oracle(sim.populations())
+    assert sim.diag()["step"] == nsteps
+    want = start.copy()
+    assert ostep.step(P, want, nsteps) == 0
+    assert rel_inf(got, want) < nsteps * STEP_TOL[prec]
     sim.close()
 
 
@@ -185,7 +220,7 @@ def test_macros_match_oracle_fields():
     sim.close()
 
 
-@pytest.mark.parametrize("variant", ["2pass-64x4", "fused-64x64", "fused2-128x32"])
+@pytest.mark.parametrize("variant", ["2pass-64x4", "fused-64x64", "fused2-128x32", "twostep-58x64"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_batch_equals_alone_bitwise(prec, variant):
     """Uneven grids stepped together give the bits of each stepped alone, also
