@@ -75,3 +75,41 @@ def test_a_failing_request_is_isolated():
         s.step(q.steps)
         assert torch.equal(r.state, s.populations().cpu()), q.id
         s.close()
+
+
+def test_autotuned_server_takes_odd_widths_after_an_even_sample():
+    """The server's autotuner, run on requests of even width only, picks a
+    variant that still accepts the odd-width request (nx = 77) that arrives
+    later; every request completes."""
+    be = GpuBackend(precision="fp32", max_instances=8, max_tiles=1 << 14, n_batches=2, write_through=True)
+    even = [r for r in _requests() if r.nx % 2 == 0]
+    variant, mlups = be.autotune(even, reps=8)
+    assert not L.variant_names()[variant].startswith("fused2") and mlups > 0
+    srv = Server(be, budget_bytes=10 ** 9, max_slots=8, chunk_steps=128)
+    results, stats = srv.run(_requests())
+    be.close()
+    assert len(results) == 5 and stats["failed"] == 0
+    assert [r.diag["step"] for r in results] == [q.steps for q in _requests()]
+
+
+def test_served_binary32_results_within_1e4_of_binary64():
+    """Each served binary32 result (radius, mass, wall-pressure peak) against
+    the same request stepped alone in binary64 (the path held to the oracle
+    at 1e-12): within the 1e-4 the binary32 path is held to."""
+    from importlib import util
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = util.spec_from_file_location("bench_under_test", os.path.join(root, "bench.py"))
+    bench = util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    be = GpuBackend(precision="fp32", max_instances=8, max_tiles=1 << 14, n_batches=2, write_through=True,
+                    variant=L.variant_names().index("fused-64x16"))
+    srv = Server(be, budget_bytes=10 ** 9, max_slots=8, chunk_steps=128)
+    results, _ = srv.run(_requests())
+    be.close()
+    errs = bench.served_reference_errors("cuda:0", _requests(), results)
+    assert len(errs["per_request"]) == 5
+    for e in errs["per_request"]:
+        print(e, flush=True)
+        assert e["radius"] < 1e-4 and e["mass"] < 1e-4
+        assert e["wall_p"] is None or e["wall_p"] < 1e-4

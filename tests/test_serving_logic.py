@@ -168,3 +168,15 @@ def test_failed_requests_are_retired_after_their_first_chunk():
             assert not r.failed and r.diag["step"] == q.steps
     assert stats["site_updates"] == sum(q.sites * (500 if q.id in (3, 7) else q.steps) for q in reqs)
     assert be.resident == 0
+
+
+def test_served_autotune_candidates_accept_any_width():
+    """The served autotuner only weighs variants that take odd grid widths, so
+    a pick made on a sample of even widths cannot refuse a later request."""
+    from paper_1605_01800_amd.serving import served_variants
+    names = ["2pass-64x4", "fused-64x16", "fused2-128x16", "fused2-128x32", "fused-64x32"]
+    assert served_variants(names) == [0, 1, 4]
+    L = pytest.importorskip("paper_1605_01800_amd.lbm")
+    all_names = L.variant_names()
+    picks = served_variants(all_names)
+    assert picks and all(not all_names[i].startswith("fused2") for i in picks)
