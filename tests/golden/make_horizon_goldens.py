@@ -24,6 +24,7 @@ arithmetic.  Every stored value is the oracle's.  The wall time of every run is
 stored with the thread count and the CPU model.
 
     python tests/golden/make_horizon_goldens.py sweep|collapse [--delta D --seed S] [--threads N]
+                                                [--out DIR]   (default: tests/golden)
 """
 import argparse
 import os
@@ -40,12 +41,18 @@ sys.path.insert(0, ROOT)
 from oracle import coexist, diagnostics, stepper  # noqa: E402
 from paper_1605_01800_amd import inputs  # noqa: E402
 
-SWEEP_FILE = os.path.join(HERE, "laplace_sweep_40k.npz")
+OUT_DIR = HERE
+
+
+def sweep_file():
+    return os.path.join(OUT_DIR, "laplace_sweep_40k.npz")
+
+
 SNAP_STEPS = (1000, 5000, 10000, 20000, 50000)
 
 
 def collapse_file(delta, seed):
-    return os.path.join(HERE, "collapse_1024x768_50k_d%03d_s%d.npz" % (round(delta * 1000), seed))
+    return os.path.join(OUT_DIR, "collapse_1024x768_50k_d%03d_s%d.npz" % (round(delta * 1000), seed))
 
 
 def cpu_model():
@@ -117,11 +124,11 @@ def run_sweep(steps=40000, every=1000):
                  meta["dp"][i]), flush=True)
     total = float(np.sum(meta["wall_s"]))
     np.savez_compressed(
-        SWEEP_FILE, steps=steps, every=every, stride=4, radius=radius, mass=mass,
+        sweep_file(), steps=steps, every=every, stride=4, radius=radius, mass=mass,
         rho_sampled=rho_s.astype(np.float32), rho_centre_row=row_c, rho_centre_col=col_c,
         threads=stepper.threads(), cpu=cpu_model(), total_wall_s=total,
         mlups=ncase * n * n * steps / total / 1e6, **meta)
-    print("wrote", SWEEP_FILE, "oracle %.2f MLUPS on %d threads" % (ncase * n * n * steps / total / 1e6,
+    print("wrote", sweep_file(), "oracle %.2f MLUPS on %d threads" % (ncase * n * n * steps / total / 1e6,
                                                                       stepper.threads()), flush=True)
 
 
@@ -183,7 +190,11 @@ def main():
     ap.add_argument("--delta", type=float, default=0.02)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--out", default=HERE)
     a = ap.parse_args()
+    global OUT_DIR
+    OUT_DIR = a.out
+    os.makedirs(OUT_DIR, exist_ok=True)
     if a.threads > 0:
         stepper.set_threads(a.threads)
     if a.what == "sweep":

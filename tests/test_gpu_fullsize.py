@@ -267,3 +267,20 @@ def test_batch_group_equals_one_batch_bitwise():
             s.close()
     for a, b in zip(*out):
         assert np.array_equal(a, b)
+
+
+def test_precision_study_large_grid_reduced_steps():
+    """The 8192 x 4096 three-disc collapse (T = 0.6 T_c, delta = 0.02, tau_nu =
+    0.6) over its first 2000 steps in binary32 and in binary32 with binary64
+    EOS and psi near the spinodal, against the binary64 GPU path (held to the
+    oracle at 1e-12): total mass, every bubble's radius history and the
+    wall-pressure peak within 1e-4."""
+    print("case precision large", flush=True)
+    out = studies.precision_study("cuda:0", True, steps=2000, every=250)
+    for prec in ("fp32", "fp32_mixed"):
+        e = out["runs"][prec]
+        print(prec, e["mass_max_rel_err"], e["radius_max_rel_err"], e.get("wall_p_max_rel_err"), flush=True)
+        assert not e["nonfinite"] and e["steps_done"] == 2000
+        assert e["mass_max_rel_err"] < 1e-4
+        assert max(e["radius_max_rel_err"]) < 1e-4
+        assert e["wall_p_max_rel_err"] < 1e-4
