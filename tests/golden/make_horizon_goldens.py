@@ -25,6 +25,9 @@ stored with the thread count and the CPU model.
 
     python tests/golden/make_horizon_goldens.py sweep|collapse [--delta D --seed S] [--threads N]
                                                 [--out DIR]   (default: tests/golden)
+    python tests/golden/make_horizon_goldens.py sweep --part I --parts N   (cases I, I+N, ...)
+    python tests/golden/make_horizon_goldens.py merge-sweep --parts N      (joins the parts)
+    python tests/golden/make_horizon_goldens.py timing [--max-steps K]     (1 thread and all)
 """
 import argparse
 import os
@@ -70,9 +73,42 @@ def sample(rho, stride=4):
     return np.ascontiguousarray(rho[::stride, ::stride])
 
 
-def run_sweep(steps=40000, every=1000):
+SWEEP_PER_CASE = ("radius", "mass", "rho_sampled", "rho_centre_row", "rho_centre_col", "T_over_Tc", "T", "R",
+                  "slab_rows", "rho_l", "rho_g", "dp", "p_in", "p_out", "slab_rho_g", "slab_rho_l", "wall_s")
+
+
+def part_file(i):
+    return os.path.join(OUT_DIR, "laplace_sweep_40k_part%d.npz" % i)
+
+
+def merge_sweep(parts):
+    """Joins the parts written by `sweep --part i --parts n` (cases i, i + n,
+    ...) into the one reference file, in case order."""
+    ps = [np.load(part_file(i), allow_pickle=False) for i in range(parts)]
+    ncase = sum(len(p["case_index"]) for p in ps)
+    out = {}
+    for key in SWEEP_PER_CASE:
+        a = None
+        for p in ps:
+            v = p[key]
+            if a is None:
+                a = np.zeros((ncase,) + v.shape[1:], dtype=v.dtype)
+            a[p["case_index"]] = v
+        out[key] = a
+    total = float(np.sum(out["wall_s"]))
     n = 256
-    cases = inputs.laplace_sweep_cases(n)
+    steps = int(ps[0]["steps"])
+    np.savez_compressed(sweep_file(), steps=steps, every=int(ps[0]["every"]), stride=4,
+                        threads=int(ps[0]["threads"]), cpu=str(ps[0]["cpu"]), total_wall_s=total,
+                        mlups=ncase * n * n * steps / total / 1e6, **out)
+    print("wrote", sweep_file(), "oracle %.2f MLUPS" % (ncase * n * n * steps / total / 1e6), flush=True)
+
+
+def run_sweep(steps=40000, every=1000, part=0, parts=1):
+    n = 256
+    all_cases = inputs.laplace_sweep_cases(n)
+    index = list(range(part, len(all_cases), parts))
+    cases = [all_cases[i] for i in index]
     ncase = len(cases)
     nrec = steps // every + 1
     radius = np.full((ncase, nrec), np.nan)
@@ -124,12 +160,13 @@ def run_sweep(steps=40000, every=1000):
                  meta["dp"][i]), flush=True)
     total = float(np.sum(meta["wall_s"]))
     np.savez_compressed(
-        sweep_file(), steps=steps, every=every, stride=4, radius=radius, mass=mass,
+        sweep_file() if parts == 1 else part_file(part), case_index=np.array(index),
+        steps=steps, every=every, stride=4, radius=radius, mass=mass,
         rho_sampled=rho_s.astype(np.float32), rho_centre_row=row_c, rho_centre_col=col_c,
         threads=stepper.threads(), cpu=cpu_model(), total_wall_s=total,
         mlups=ncase * n * n * steps / total / 1e6, **meta)
-    print("wrote", sweep_file(), "oracle %.2f MLUPS on %d threads" % (ncase * n * n * steps / total / 1e6,
-                                                                      stepper.threads()), flush=True)
+    print("wrote", sweep_file() if parts == 1 else part_file(part),
+          "oracle %.2f MLUPS on %d threads" % (ncase * n * n * steps / total / 1e6, stepper.threads()), flush=True)
 
 
 def run_collapse(delta, seed, steps=50000, every=100):
@@ -184,9 +221,46 @@ def run_collapse(delta, seed, steps=50000, every=100):
                                                                     stepper.threads(), wall), flush=True)
 
 
+def run_timing(max_steps):
+    """Oracle MLUPS on the three parity workloads, on one thread and on all
+    the threads of its OpenMP runtime: the 64 x 64 binary64 check case
+    (10,000 steps, in full), one instance of the sweep (256 x 256, R = 40 at
+    0.7 T_c) and the 1024 x 768 collapse, each for min(its steps, max_steps)
+    steps (the full sweep and collapse runs are timed when their references
+    are written)."""
+    nthreads = stepper.threads()
+    cases = []
+    T7 = coexist.temperature(0.7)
+    rg, rl, _ = coexist.maxwell(T7)
+    P = stepper.make_params(64, 64, T7, tau_nu=0.8)
+    cases.append(("64x64 periodic, binary64, 10000 steps", P,
+                  dict(bubbles=[(31.5, 31.5, 16.0)], rho_l=rl, rho_g=rg, W=2.0), 10000))
+    P = stepper.make_params(256, 256, T7, tau_nu=0.6)
+    cases.append(("256x256 sweep instance", P, dict(bubbles=[(127.5, 127.5, 40.0)], rho_l=rl, rho_g=rg, W=5.0),
+                  min(40000, max_steps)))
+    T6 = coexist.temperature(0.6)
+    g6, l6, _ = coexist.maxwell(T6)
+    P = stepper.make_params(1024, 768, T6, walls=True, tau_nu=0.6)
+    cases.append(("1024x768 collapse", P, dict(bubbles=[(511.5, 200.0, 120.0)], rho_l=l6, rho_g=g6, W=5.0,
+                                                delta=0.02, noise_amp=1e-3, seed=1), min(50000, max_steps)))
+    for name, P, init, steps in cases:
+        for th in (1, nthreads):
+            stepper.set_threads(th)
+            f = stepper.init_populations(P, stepper.init_density(P, **init))
+            t0 = time.perf_counter()
+            assert stepper.step(P, f, steps) == 0
+            dt = time.perf_counter() - t0
+            print("oracle timing: %s, %d steps, %d thread(s): %.1f s, %.2f MLUPS (%s)"
+                  % (name, steps, th, dt, P.nx * P.ny * steps / dt / 1e6, cpu_model()), flush=True)
+    stepper.set_threads(nthreads)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["sweep", "collapse"])
+    ap.add_argument("what", choices=["sweep", "collapse", "merge-sweep", "timing"])
+    ap.add_argument("--max-steps", type=int, default=2000)
+    ap.add_argument("--part", type=int, default=0)
+    ap.add_argument("--parts", type=int, default=1)
     ap.add_argument("--delta", type=float, default=0.02)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--threads", type=int, default=0)
@@ -198,7 +272,11 @@ def main():
     if a.threads > 0:
         stepper.set_threads(a.threads)
     if a.what == "sweep":
-        run_sweep()
+        run_sweep(part=a.part, parts=a.parts)
+    elif a.what == "merge-sweep":
+        merge_sweep(a.parts)
+    elif a.what == "timing":
+        run_timing(a.max_steps)
     else:
         run_collapse(a.delta, a.seed)
 
