@@ -168,10 +168,36 @@ __device__ __forceinline__ int src_buffer(const InstDev &d, int s)
 // |f - w rho_ref| / |f| smaller (three orders of magnitude in the liquid).
 //
 // sum_a g_a = rho - rho_ref, always in this order.
+//
+// Mirror-symmetric rounding.  Every sum over populations below is written
+// as a tree that a reflection of the lattice (x -> -x swaps 1 <-> 3, 5 <-> 6,
+// 7 <-> 8; y -> -y swaps 2 <-> 4, 5 <-> 8, 6 <-> 7) maps onto itself, up to
+// the order of the two operands of an addition (which does not change a
+// rounded sum) and up to an exact sign change.  A state that is symmetric
+// under a reflection then stays symmetric bit for bit, as the exact
+// dynamics does: a disc or slab at the centre of a periodic grid cannot
+// drift by accumulating rounding errors that favour one side.  (Written in
+// population order instead, the binary32 path moved such interfaces by up to
+// 6e-3 sites in 40,000 steps, which shows as 1.7e-3 of the density range at
+// the interface.)
 template <typename T>
 __device__ __forceinline__ T density(const T v[9])
 {
-    return (((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]))) + v[8];
+    return (((v[1] + v[3]) + (v[2] + v[4])) + ((v[5] + v[7]) + (v[6] + v[8]))) + v[0];
+}
+
+// Momentum sums of Eq. 6 in mirror-symmetric form: an x reflection negates
+// jx exactly and leaves jy unchanged, a y reflection the reverse.
+template <typename T>
+__device__ __forceinline__ T momentum_x(const T v[9])
+{
+    return (v[1] - v[3]) + ((v[5] + v[8]) - (v[6] + v[7]));
+}
+
+template <typename T>
+__device__ __forceinline__ T momentum_y(const T v[9])
+{
+    return (v[2] - v[4]) + ((v[5] + v[6]) - (v[7] + v[8]));
 }
 
 // 1/x and sqrt(x).  In binary64 correctly rounded.  In binary32 the hardware
@@ -333,8 +359,8 @@ __device__ __forceinline__ void collide_site(T f[9], T psi_c, T Fx, T Fy, const 
 {
     const T dm = density<T>(f);                 // rho - rho_ref
     const T rho = R.rho_ref + dm;
-    const T jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-    const T jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    const T jx = momentum_x<T>(f);
+    const T jy = momentum_y<T>(f);
     const T inv_rho = recip(rho);
     // Eq. 6 with delta_t = 1
     const T vx = (jx + T(0.5) * Fx) * inv_rho;
@@ -342,13 +368,14 @@ __device__ __forceinline__ void collide_site(T f[9], T psi_c, T Fx, T Fy, const 
     const T v2 = vx * vx + vy * vy;
 
     // non-conserved moments m = M f
-    const T axis = (f[1] + f[2]) + (f[3] + f[4]);
-    const T diag = (f[5] + f[6]) + (f[7] + f[8]);
+    // (each sum a mirror-symmetric tree, as in density())
+    const T axis = (f[1] + f[3]) + (f[2] + f[4]);
+    const T diag = (f[5] + f[7]) + (f[6] + f[8]);
     const T m1 = T(-4) * f[0] - axis + T(2) * diag;
     const T m2 = T(4) * f[0] - T(2) * axis + diag;
-    const T m4 = T(2) * (f[3] - f[1]) + (f[5] - f[6]) + (f[8] - f[7]);
-    const T m6 = T(2) * (f[4] - f[2]) + (f[5] + f[6]) - (f[7] + f[8]);
-    const T m7 = (f[1] - f[2]) + (f[3] - f[4]);
+    const T m4 = T(2) * (f[3] - f[1]) + ((f[5] + f[8]) - (f[6] + f[7]));
+    const T m6 = T(2) * (f[4] - f[2]) + ((f[5] + f[6]) - (f[7] + f[8]));
+    const T m7 = (f[1] + f[3]) - (f[2] + f[4]);
     const T m8 = (f[5] - f[6]) + (f[7] - f[8]);
 
     // equilibria, Eq. 4 (e and zeta rows shifted by 2 rho_ref and -rho_ref,
@@ -551,7 +578,8 @@ __global__ __launch_bounds__(BLOCK) void collide_stream_kernel(const InstDev *__
 // handled now is formed before the collision, so that the loads it waits for
 // are the last ones issued before the prefetch.  The two ring columns left and
 // right of the strip are loaded one population per lane (lanes 0-8 and 16-24;
-// the other lanes load a copy that is not used) and summed across lanes.
+// the other lanes load a copy that is not used) and summed across lanes into
+// lanes 1 and 17.
 //
 // Ring hazards: in iteration k the block writes psi of rows y0-1+4k .. y0+2+4k
 // and reads rows y0+4k-10 .. y0+4k-5, all written before the previous
@@ -579,16 +607,35 @@ __device__ __forceinline__ double row_next(double v)
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
+// The value of lane i - N of the same 16-lane row (a DPP row shift the other
+// way); lanes whose source lies outside the row get 0.
+template <int N>
+__device__ __forceinline__ float row_prev(float v)
+{
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x110 + N, 0xF, 0xF, true));
+}
+
+template <int N>
+__device__ __forceinline__ double row_prev(double v)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, 0x110 + N, 0xF, 0xF, true);
+    const unsigned hi =
+        (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), 0x110 + N, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // Lanes b .. b+8 (b = 0 or 16) hold populations 0..8 of one ring column;
-// returns in lane b the column's rho - rho_ref, summed in the order of
+// returns in lane b + 1 the column's rho - rho_ref, summed in the order of
 // density().  Every lane of the wavefront must call it.
 template <typename T>
 __device__ __forceinline__ T halo_density(T v)
 {
-    const T s1 = v + row_next<1>(v);          // lane b + 2i: v2i + v2i+1
-    const T s2 = s1 + row_next<2>(s1);        // lane b + 4i: pairs of pairs
-    const T s3 = s2 + row_next<4>(s2);        // lane b: v0 + ... + v7
-    return s3 + row_next<8>(v);
+    const T s1 = v + row_next<2>(v);          // lanes b+1, b+2, b+5, b+6: v1+v3, v2+v4, v5+v7, v6+v8
+    const T s2 = s1 + row_next<1>(s1);        // lanes b+1, b+5: the axis and the diagonal sums
+    const T s3 = s2 + row_next<4>(s2);        // lane b+1: the eight moving populations
+    return s3 + row_prev<1>(v);               // lane b+1: plus v0 from lane b
 }
 
 // Memory row of lattice row l (ghost rows -1 and ny mirror at walls, wrap
@@ -634,8 +681,8 @@ __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict_
     const bool hlane = lane < 32 && hp < 9;
     const int hcol = lane < 16 ? (tl.x0 == 0 ? nx - 1 : tl.x0 - 1) : (tl.x0 + TILE_X) % nx;
     const unsigned long long hoff = (unsigned long long)(hlane ? hp : 0) * PB + (unsigned)hcol * sizeof(T);
-    const bool hroot = lane == 0 || lane == 16;
-    const int hslot = lane == 0 ? 0 : LW - 1;
+    const bool hroot = lane == 1 || lane == 17;
+    const int hslot = lane == 1 ? 0 : LW - 1;
     const int y_end = min(tl.y0 + H, ny);                     // rows collided: [y0, y_end)
     const bool track = walls && (tl.y0 == 0 || tl.y0 + H >= ny);
     const Consts<T> &R = consts<T>(d);
@@ -876,8 +923,8 @@ __global__ __launch_bounds__(BLOCK) void fused2_kernel(const InstDev *__restrict
     const bool hlane = lane < 32 && hp < 9;
     const int hcol = lane < 16 ? (tl.x0 == 0 ? nx - 1 : tl.x0 - 1) : (tl.x0 + SW) % nx;
     const unsigned long long hoff = (unsigned long long)(hlane ? hp : 0) * PB + (unsigned)hcol * sizeof(T);
-    const bool hroot = lane == 0 || lane == 16;
-    const int hslot = lane == 0 ? 0 : LW - 1;
+    const bool hroot = lane == 1 || lane == 17;
+    const int hslot = lane == 1 ? 0 : LW - 1;
     const int y_end = min(tl.y0 + H, ny);
     const bool track = walls && (tl.y0 == 0 || tl.y0 + H >= ny);
     const Consts<T> &R = consts<T>(d);
@@ -1416,8 +1463,8 @@ __global__ __launch_bounds__(BLOCK) void macros_kernel(const InstDev *__restrict
         for (int a = 0; a < 9; ++a) v[a] = f[a * P + i];
         const T dm = density<T>(v);
         const T rho = consts<T>(d).rho_ref + dm;
-        const T jx = (v[1] - v[3]) + (v[5] - v[6]) + (v[8] - v[7]);
-        const T jy = (v[2] - v[4]) + (v[5] + v[6]) - (v[7] + v[8]);
+        const T jx = momentum_x<T>(v);
+        const T jy = momentum_y<T>(v);
         auto ps = [&](int dx, int dy) -> T {
             int xx = x + dx;
             xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);

@@ -233,7 +233,7 @@ def run_timing(max_steps):
     T7 = coexist.temperature(0.7)
     rg, rl, _ = coexist.maxwell(T7)
     P = stepper.make_params(64, 64, T7, tau_nu=0.8)
-    cases.append(("64x64 periodic, binary64, 10000 steps", P,
+    cases.append(("64x64 periodic, binary64", P,
                   dict(bubbles=[(31.5, 31.5, 16.0)], rho_l=rl, rho_g=rg, W=2.0), 10000))
     P = stepper.make_params(256, 256, T7, tau_nu=0.6)
     cases.append(("256x256 sweep instance", P, dict(bubbles=[(127.5, 127.5, 40.0)], rho_l=rl, rho_g=rg, W=5.0),

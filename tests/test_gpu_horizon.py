@@ -98,18 +98,37 @@ def test_sweep_radius_and_mass_histories(sweep_run):
     er = np.abs(radius[disc] - g["radius"][disc]) / g["radius"][disc]
     em = np.abs(mass - g["mass"]) / g["mass"]
     print("radius history max rel err %.2e, mass %.2e" % (er.max(), em.max()), flush=True)
+    for i, case in enumerate(cases):
+        print("case %2d T/Tc %.1f: radius %.2e mass %.2e (final mass gpu %.10e oracle %.10e)"
+              % (i, case["T_over_Tc"], np.nanmax(np.abs(radius[i] - g["radius"][i]) / g["radius"][i])
+                 if disc[i] else 0.0, em[i].max(), mass[i, -1], g["mass"][i, -1]), flush=True)
     assert er.max() < TOL
     assert em.max() < TOL
+
+
+def _centroid(rho, rho_l):
+    """Centre of the density deficit rho_l - rho (x, y) of a sampled field."""
+    d = np.clip(rho_l - rho, 0.0, None)
+    yy, xx = np.mgrid[0:rho.shape[0], 0:rho.shape[1]]
+    return float(np.sum(d * xx) / np.sum(d)), float(np.sum(d * yy) / np.sum(d))
 
 
 def test_sweep_final_density_fields(sweep_run):
     g, cases, _, _, rho, _ = sweep_run
     worst = 0.0
-    for i in range(len(cases)):
+    for i, case in enumerate(cases):
         ref_s = g["rho_sampled"][i].astype(np.float64)
         scale = max(np.max(np.abs(g["rho_centre_row"][i])), np.max(np.abs(ref_s)))
-        e = max(np.max(np.abs(rho[i][::4, ::4] - ref_s)), np.max(np.abs(rho[i][128] - g["rho_centre_row"][i])),
-                np.max(np.abs(rho[i][:, 128] - g["rho_centre_col"][i]))) / scale
+        e_row = np.abs(rho[i][128] - g["rho_centre_row"][i])
+        e_col = np.abs(rho[i][:, 128] - g["rho_centre_col"][i])
+        e = max(np.max(np.abs(rho[i][::4, ::4] - ref_s)), np.max(e_row), np.max(e_col)) / scale
+        cg = _centroid(rho[i][::4, ::4], float(g["rho_l"][i]))
+        co = _centroid(ref_s, float(g["rho_l"][i]))
+        print("case %2d T/Tc %.1f R %2g slab %3d: max rel err %.2e (row max at x=%d, column max at y=%d), "
+              "deficit centre shift (%.2e, %.2e) sites"
+              % (i, case["T_over_Tc"], case["bubbles"][0][2] if case["bubbles"] else 0, case["slab_rows"], e,
+                 int(np.argmax(e_row)), int(np.argmax(e_col)), 4 * (cg[0] - co[0]), 4 * (cg[1] - co[1])),
+              flush=True)
         worst = max(worst, e)
     print("final density fields max rel err %.2e" % worst, flush=True)
     assert worst < TOL

@@ -504,3 +504,31 @@ def test_mixed_precision_uses_binary64_only_in_the_spinodal_interval(variant):
             assert rel_inf(to_oracle(got), want) < STEP_TOL[prec]
             sim.close()
         assert np.array_equal(out["fp32"], out["fp32_mixed"]) == same
+
+
+# mirror images of the D2Q9 directions: x -> -x and y -> -y
+_MIRROR_X = [0, 3, 2, 1, 4, 6, 5, 8, 7]
+_MIRROR_Y = [0, 1, 4, 3, 2, 8, 7, 6, 5]
+
+
+@pytest.mark.parametrize("variant", ["2pass-64x4", "fused-64x16", "fused2-128x16", "twostep-58x24"])
+@pytest.mark.parametrize("prec,walls", [("fp32", False), ("fp32", True), ("fp64", False), ("fp32_mixed", True)])
+def test_mirror_symmetric_state_stays_bitwise_symmetric(prec, walls, variant):
+    """A disc at the centre of the grid is symmetric under both reflections
+    (with walls, the walls are the y mirror's planes too); every kernel's
+    rounding is mirror-symmetric, so after 3001 steps the populations are
+    still bit for bit their own mirror images (population a at (x, y) equals
+    the mirrored population at the mirrored site): the disc cannot drift."""
+    print("case mirror", prec, walls, variant, flush=True)
+    nx, ny = 96, 70
+    p = L.make_params(nx, ny, T_over_Tc=0.7, walls=walls, precision=prec, tau_nu=0.6)
+    s = L.Sim(p)
+    s.set_variant(_variant(variant))
+    s.init_bubble([(0.5 * (nx - 1), 0.5 * (ny - 1), 17.0)], W=5.0, delta=0.01 if walls else 0.0)
+    s.step(3001)
+    f = s.populations().cpu()
+    s.close()
+    fx = f[_MIRROR_X].flip(2)
+    fy = f[_MIRROR_Y].flip(1)
+    assert torch.equal(f, fx)
+    assert torch.equal(f, fy)
