@@ -221,18 +221,14 @@ void fill_consts(Consts<T> &c, const InstDev &d)
     c.li_e = (T)d.li_e;
     c.li_z = (T)d.li_z;
     const double c9 = 1.0 / 36.0, c12 = 1.0 / 12.0, c4 = 0.25;
-    c.e_m = (T)((1.0 - d.s_e) * c9);
     c.e_eq = (T)(d.s_e * c9);
     c.e_vf = (T)(6.0 * (1.0 - 0.5 * d.s_e) * c9);
     c.e_li = (T)(d.li_e * c9);
-    c.z_m = (T)((1.0 - d.s_z) * c9);
     c.z_eq = (T)(d.s_z * c9);
     c.z_vf = (T)(-6.0 * (1.0 - 0.5 * d.s_z) * c9);
     c.z_li = (T)(-d.li_z * c9);
-    c.q_m = (T)((1.0 - d.s_q) * c12);
     c.q_eq = (T)(d.s_q * c12);
     c.q_f = (T)(-(1.0 - 0.5 * d.s_q) * c12);
-    c.n_m = (T)((1.0 - d.s_nu) * c4);
     c.n_eq = (T)(d.s_nu * c4);
     c.n_xx = (T)(2.0 * (1.0 - 0.5 * d.s_nu) * c4);
     c.n_xy = (T)((1.0 - 0.5 * d.s_nu) * c4);

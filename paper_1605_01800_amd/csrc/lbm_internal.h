@@ -35,13 +35,14 @@ struct Consts {
     T h_e, h_z, h_q, h_nu;         // 1 - s/2
     T li_e, li_z;                  // Li's term after (I - Lambda/2): s 0.75 eps
     // Relaxation (Eq. 3) and the scale c_k of the inverse transform folded
-    // together: c_k m*_k = (1 - s_k) c_k m_k + s_k c_k m_eq_k + c_k (1 - s_k/2) S_k,
-    // with c = 1/36 (e, zeta), 1/12 (q), 1/4 (pxx, pxy); the *_vf, *_li, *_f,
-    // *_xx and *_xy factors multiply the parts of S_k of Eq. 14.
-    T e_m, e_eq, e_vf, e_li;       // e row
-    T z_m, z_eq, z_vf, z_li;       // zeta row
-    T q_m, q_eq, q_f;              // qx, qy rows
-    T n_m, n_eq, n_xx, n_xy;       // pxx, pxy rows
+    // together, as increments: c_k (m*_k - m_k) = s_k c_k (m_eq_k - m_k)
+    // + c_k (1 - s_k/2) S_k, with c = 1/36 (e, zeta), 1/12 (q), 1/4 (pxx,
+    // pxy); the *_vf, *_li, *_f, *_xx and *_xy factors multiply the parts of
+    // S_k of Eq. 14.
+    T e_eq, e_vf, e_li;            // e row
+    T z_eq, z_vf, z_li;            // zeta row
+    T q_eq, q_f;                   // qx, qy rows
+    T n_eq, n_xx, n_xy;            // pxx, pxy rows
 };
 
 // Device-visible description of one instance.  The host keeps a mirror and

