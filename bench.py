@@ -51,58 +51,71 @@ def timing_parts(steps):
     return [256] * full + ([rest] if rest else [])
 
 
-_SLEEP_CYCLES_PER_MS = None
+def hold(L, streams, ms):
+    """Holds every stream until one common instant of the device clock, about
+    `ms` milliseconds ahead (lbm_hold_until): the host enqueues the timed
+    region's first part on every stream meanwhile, and the streams then start
+    together, so that the region times the device work alone, neither the
+    host's enqueueing nor a cross-stream wait (a fork of four streams from one
+    and their join back cost about 30 us, measured with tiny kernels)."""
+    tick, rate = L.device_clock()
+    until = tick + int(ms * 1e-3 * rate)
+    for st in streams:
+        L.hold_until(until, rate // 2, st)
 
 
-def gate(torch, stream, ms):
-    """Holds `stream` for about `ms` milliseconds with a spin kernel, so that
-    the host has enqueued the whole timed region (graph launches on every
-    stream, events) before the GPU reaches its first event: the region then
-    times the device work alone, not the host's enqueueing.  The spin kernel
-    runs before the region's first event."""
-    global _SLEEP_CYCLES_PER_MS
-    with torch.cuda.stream(stream):
-        if _SLEEP_CYCLES_PER_MS is None:
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            torch.cuda._sleep(1000000)
-            e1.record(stream)
-            e1.synchronize()
-            _SLEEP_CYCLES_PER_MS = 1000000 / max(e0.elapsed_time(e1), 1e-3)
-        torch.cuda._sleep(int(ms * _SLEEP_CYCLES_PER_MS))
-
-
-def timed_region(torch, runner, main, group, steps, warmup):
-    """Times `steps` steps of `runner` (a Batch, or a BatchGroup given also as
-    `group`) with HIP events on stream `main`; returns (ms, median ms per step
-    of the parts, parts).  The warm-up runs `warmup` steps, then readies the
-    timed steps' graphs and descriptors without running them
+def timed_region(torch, L, runner, streams, steps, warmup):
+    """Times `steps` steps of `runner` (a Batch on streams[0], or a
+    BatchGroup whose batches run on `streams`) with HIP events; returns (ms,
+    median ms per step of the parts, parts).  The warm-up runs `warmup` steps,
+    then readies the timed steps' graphs and descriptors without running them
     (lbm_batch_prepare), so the timed region enqueues nothing but graph
-    launches.  The timed steps run as parts of up to 256 steps with events
-    between them (the whole region gives the time; the parts give a median).
-    With several streams every part starts after the previous one has ended
-    on all of them (fork from and join into `main`)."""
+    launches.  The timed steps run as parts of up to 256 steps.  Every stream
+    records a start event after the common hold and an end event after its
+    last part; the region runs from the earliest start to the latest end, so
+    it brackets the work of every stream without timing a cross-stream wait.
+    Between parts the streams are aligned again (the first waits for the
+    others, they for it; events without timing, which cost less in a busy
+    stream), and the first stream records a timed event there: left to drift
+    apart, four concurrent batches ran 3 % slower over 1280 steps.  The parts
+    add up to the region (for the median)."""
     parts = timing_parts(steps)
     if warmup > 0:
         runner.step(warmup)
     runner.prepare(steps)
     runner.sync()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(parts) + 1)]
+    start = [torch.cuda.Event(enable_timing=True) for _ in streams]
+    end = [torch.cuda.Event(enable_timing=True) for _ in streams]
+    mid = [torch.cuda.Event(enable_timing=True) for _ in parts[1:]]
     torch.cuda.synchronize()
-    n_streams = len(group.batches) if group is not None else 1
-    gate(torch, main, max(1.0, 0.25 * len(parts) * n_streams))
-    ev[0].record(main)
-    for i, n in enumerate(parts, start=1):
-        if group is not None:
-            group.fork(ev[i - 1])
+    ref = torch.cuda.Event(enable_timing=True)
+    ref.record(streams[0])                  # before every hold ends
+    # long enough for the host to enqueue the first part on every stream (the
+    # later parts are enqueued while it runs), and no longer: an idle device
+    # lowers its clocks, and after a 20 ms hold the first 512 steps ran 10 %
+    # slower
+    hold(L, streams, max(1.0, 0.5 * len(streams)))
+    for e, st in zip(start, streams):
+        e.record(st)
+    for i, n in enumerate(parts):
+        if i > 0:
+            for st in streams[1:]:
+                done = torch.cuda.Event()
+                done.record(st)
+                streams[0].wait_event(done)
+            mid[i - 1].record(streams[0])
+            go = torch.cuda.Event()
+            go.record(streams[0])
+            for st in streams[1:]:
+                st.wait_event(go)
         runner.step(n)
-        if group is not None:
-            group.join(main)
-        ev[i].record(main)
-    ev[-1].synchronize()
-    ms = ev[0].elapsed_time(ev[-1])
-    part_ms = sorted(ev[i - 1].elapsed_time(ev[i]) / n for i, n in enumerate(parts, start=1))
+    for e, st in zip(end, streams):
+        e.record(st)
     torch.cuda.synchronize()
+    bounds = ([min(ref.elapsed_time(e) for e in start)] + [ref.elapsed_time(e) for e in mid] +
+              [max(ref.elapsed_time(e) for e in end)])            # ms after `ref`
+    ms = bounds[-1] - bounds[0]
+    part_ms = sorted((bounds[i + 1] - bounds[i]) / n for i, n in enumerate(parts))
     return ms, part_ms[len(part_ms) // 2], len(part_ms)
 
 
@@ -514,7 +527,7 @@ def main():
     # dominant kernel's launch duration for the roofline, and matches a
     # kernel trace launch for launch (a profiler serialises concurrent
     # streams, so their launches cannot be checked against a trace).
-    ms1, median1, nparts1 = timed_region(torch, batch, batch.stream, None, args.steps, args.warmup)
+    ms1, median1, nparts1 = timed_region(torch, L, batch, [batch.stream], args.steps, args.warmup)
     for s in sims:
         s.sync()                          # raises if a non-finite value was latched
     print("# one stream, %d steps: %.4f ms/step, %.0f MLUPS" % (args.steps, ms1 / args.steps,
@@ -531,7 +544,7 @@ def main():
         group.set_variant(variant)
         group_wt = group.batches[0].write_through
         workload["write_through"] = group_wt
-        ms, median_ms, nparts = timed_region(torch, group, group.streams[0], group, args.steps, args.warmup)
+        ms, median_ms, nparts = timed_region(torch, L, group, group.streams, args.steps, args.warmup)
     else:
         ms, median_ms, nparts = ms1, median1, nparts1
     for s in sims:

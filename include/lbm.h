@@ -337,6 +337,19 @@ int lbm_mechanical_stability(double a, double b, double R, double T, double G, d
  * count.  Asynchronous. */
 int lbm_copy_kernel(void *d_dst, const void *d_src, size_t n, void *hip_stream);
 
+/* The current device's constant-rate clock: *tick its present value (read by
+ * a one-thread kernel, waited for), *rate_hz its frequency.  Synchronous.
+ * With lbm_hold_until, for timing work on several streams from one common
+ * instant. */
+int lbm_device_clock(uint64_t *tick, uint64_t *rate_hz);
+
+/* Enqueues on a stream a one-thread kernel that waits until the device clock
+ * (lbm_device_clock) reaches `tick`, or for at most `max_ticks` from its own
+ * start (at most one second's worth; LBM_EINVAL beyond), so that holds with
+ * the same `tick` on several streams release their streams together, however
+ * far apart the host enqueued them.  Asynchronous. */
+int lbm_hold_until(uint64_t tick, uint64_t max_ticks, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

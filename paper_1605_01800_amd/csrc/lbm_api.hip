@@ -1335,3 +1335,66 @@ int lbm_copy_kernel(void *d_dst, const void *d_src, size_t n, void *hip_stream)
 }
 
 }  // extern "C"
+
+namespace {
+
+// The device's constant-rate clock (the same counter on every CU), read once
+// into a variable of the library's own (no allocation, which could disturb the
+// timing it serves).
+__device__ unsigned long long g_clock_now;
+
+__global__ void clock_now_kernel()
+{
+    g_clock_now = (unsigned long long)wall_clock64();
+}
+
+// Holds its stream until the device clock reaches `until`, or for at most
+// `limit` ticks from the kernel's own start, whichever comes first: holds
+// launched on several streams with the same `until` end together, however
+// far apart the host enqueued them.
+__global__ void hold_until_kernel(unsigned long long until, unsigned long long limit)
+{
+    const unsigned long long t0 = (unsigned long long)wall_clock64();
+    for (;;) {
+        const unsigned long long t = (unsigned long long)wall_clock64();
+        if (t >= until || t - t0 >= limit) break;
+    }
+}
+
+uint64_t clock_rate_hz()
+{
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return 0;
+    return (uint64_t)khz * 1000u;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_device_clock(uint64_t *tick, uint64_t *rate_hz)
+{
+    if (!tick || !rate_hz) return LBM_EINVAL;
+    const uint64_t rate = clock_rate_hz();
+    if (rate == 0) return LBM_EHIP;
+    unsigned long long h = 0;
+    clock_now_kernel<<<1, 1, 0, nullptr>>>();
+    TRYHIP(hipGetLastError());
+    TRYHIP(hipMemcpyFromSymbol(&h, HIP_SYMBOL(g_clock_now), sizeof(h), 0, hipMemcpyDeviceToHost));
+    *tick = h;
+    *rate_hz = rate;
+    return LBM_OK;
+}
+
+int lbm_hold_until(uint64_t tick, uint64_t max_ticks, void *hip_stream)
+{
+    const uint64_t rate = clock_rate_hz();
+    if (rate == 0) return LBM_EHIP;
+    if (max_ticks > rate) return LBM_EINVAL;
+    hold_until_kernel<<<1, 1, 0, (hipStream_t)hip_stream>>>(tick, max_ticks);
+    TRYHIP(hipGetLastError());
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -117,6 +117,8 @@ _SIGS = {
     "lbm_mechanical_stability": [ctypes.c_double] * 6 + [ctypes.POINTER(ctypes.c_double)] * 3,
     "lbm_spinodals": [ctypes.c_double] * 4 + [ctypes.POINTER(ctypes.c_double)] * 2,
     "lbm_copy_kernel": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+    "lbm_device_clock": [ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)],
+    "lbm_hold_until": [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p],
 }
 
 
@@ -579,4 +581,18 @@ def copy_kernel(dst, src, nbytes, stream=None):
     """Plain device copy of nbytes (multiple of 16) with liblbm's copy kernel."""
     s = stream.cuda_stream if stream is not None else torch.cuda.current_stream().cuda_stream
     _check(lib().lbm_copy_kernel(dst.data_ptr(), src.data_ptr(), int(nbytes), s), "lbm_copy_kernel")
+
+
+def device_clock():
+    """(tick, rate in Hz) of the current device's constant-rate clock."""
+    t, r = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib().lbm_device_clock(ctypes.byref(t), ctypes.byref(r)), "lbm_device_clock")
+    return t.value, r.value
+
+
+def hold_until(tick, max_ticks, stream=None):
+    """Holds `stream` until the device clock reaches `tick` (at most
+    `max_ticks`, no more than one second's worth)."""
+    s = stream.cuda_stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    _check(lib().lbm_hold_until(int(tick), int(max_ticks), s), "lbm_hold_until")
 

@@ -1,11 +1,12 @@
 """bench.py's timed region measures the kernels, also at a short run.
 
 The region times steps replayed from graphs prepared during the warm-up
-(lbm_batch_prepare), behind a spin kernel that lets the host enqueue the whole
-region first.  At 20 timed steps after 5 warm-up steps its time per step must
-then be that of a long run (no per-part transfer or host gap inside), on one
-stream (the roofline launch) and on four concurrent streams (the `value`).
-Preparing changes neither results nor state.
+(lbm_batch_prepare), behind holds that release every stream at one instant of
+the device clock once the host has enqueued the whole region.  At 20 timed
+steps after 5 warm-up steps its time per step must then be that of a long run
+(no per-part transfer, host gap or cross-stream wait inside), on one stream
+(the roofline launch) and on four concurrent streams (the `value`).  Preparing
+changes neither results nor state.
 """
 import importlib.util
 import os
@@ -34,7 +35,7 @@ def _one_batch(sims):
                 max_tiles=sum(L.tile_count(s.params) for s in sims))
     for s in sims:
         b.attach(s)
-    b.set_variant(L.variant_names().index("fused-64x16"))
+    b.set_variant(L.variant_names().index("twostep-58x32"))
     return b
 
 
@@ -43,8 +44,8 @@ def test_short_region_times_the_kernel_on_one_stream():
     bench = _bench()
     sims = studies.laplace_sweep_sims(L, "fp32", "cuda:0")
     b = _one_batch(sims)
-    short = min(bench.timed_region(torch, b, b.stream, None, 20, 5)[0] / 20 for _ in range(3))
-    long_ = bench.timed_region(torch, b, b.stream, None, 768, 64)[0] / 768
+    short = min(bench.timed_region(torch, L, b, [b.stream], 20, 5)[0] / 20 for _ in range(3))
+    long_ = bench.timed_region(torch, L, b, [b.stream], 768, 64)[0] / 768
     _, ms_pair = b.step_timed(40)
     pair = ms_pair / 40
     print("ms/step: 20 steps %.4f, 768 steps %.4f, event pair per launch %.4f" % (short, long_, pair),
@@ -62,10 +63,9 @@ def test_short_region_times_the_kernels_on_four_streams():
     bench = _bench()
     sims = studies.laplace_sweep_sims(L, "fp32", "cuda:0")
     g = L.BatchGroup(sims, precision="fp32", n_batches=4)
-    g.set_variant(L.variant_names().index("fused-64x16"))
-    main = g.streams[0]
-    short = min(bench.timed_region(torch, g, main, g, 20, 5)[0] / 20 for _ in range(3))
-    long_ = bench.timed_region(torch, g, main, g, 768, 64)[0] / 768
+    g.set_variant(L.variant_names().index("twostep-58x32"))
+    short = min(bench.timed_region(torch, L, g, g.streams, 20, 5)[0] / 20 for _ in range(3))
+    long_ = bench.timed_region(torch, L, g, g.streams, 768, 64)[0] / 768
     print("ms/step: 20 steps %.4f, 768 steps %.4f" % (short, long_), flush=True)
     assert short < 1.15 * long_
     g.close()
@@ -97,3 +97,30 @@ def test_prepare_changes_neither_results_nor_state():
     assert sa == sb == [337] * 6
     for a, c in zip(fa, fb):
         assert np.array_equal(a, c)
+
+
+def test_holds_release_their_streams_together():
+    """lbm_hold_until on four streams with one target: each stream's next
+    event comes at the target (within 50 us of each other), not before it,
+    although the holds were enqueued one after another; a hold longer than a
+    second is refused."""
+    print("case hold", flush=True)
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in streams]
+    ref = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    tick, rate = L.device_clock()
+    assert rate > 0
+    ref.record(streams[0])
+    until = tick + int(2e-3 * rate)
+    for st in streams:
+        L.hold_until(until, rate // 2, st)
+    for e, st in zip(ev, streams):
+        e.record(st)
+    torch.cuda.synchronize()
+    t = [ref.elapsed_time(e) for e in ev]
+    print("release after the first event (ms):", ["%.4f" % v for v in t], flush=True)
+    assert max(t) - min(t) < 0.05
+    assert min(t) > 0.5
+    with pytest.raises(L.LbmError):
+        L.hold_until(until, 2 * rate, streams[0])
