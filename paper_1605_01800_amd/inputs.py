@@ -1,5 +1,5 @@
 """Seeded synthetic inputs shared by the tests, the benchmark and the serving
-driver.  Holds none of the method's arithmetic: only random layouts, request
+loop.  Holds none of the method's arithmetic: only random layouts, request
 traces and population perturbations, all from numpy generators with fixed
 seeds.
 """
