@@ -112,7 +112,7 @@ def test_holds_release_their_streams_together():
     tick, rate = L.device_clock()
     assert rate > 0
     ref.record(streams[0])
-    until = tick + int(2e-3 * rate)
+    until = tick + int(20e-3 * rate)          # far beyond the host's enqueueing
     for st in streams:
         L.hold_until(until, rate // 2, st)
     for e, st in zip(ev, streams):
@@ -121,6 +121,6 @@ def test_holds_release_their_streams_together():
     t = [ref.elapsed_time(e) for e in ev]
     print("release after the first event (ms):", ["%.4f" % v for v in t], flush=True)
     assert max(t) - min(t) < 0.05
-    assert min(t) > 0.5
+    assert min(t) > 10.0
     with pytest.raises(L.LbmError):
         L.hold_until(until, 2 * rate, streams[0])
