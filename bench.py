@@ -119,9 +119,10 @@ def timed_region(torch, L, runner, streams, steps, warmup):
     return ms, part_ms[len(part_ms) // 2], len(part_ms)
 
 
-def measured_traffic(workload, variant_name, batches):
+def measured_traffic(workload, variant_name, batches, write_through):
     """The rocprofv3 FETCH_SIZE and WRITE_SIZE record of the dominant kernel
-    for this workload, tile variant and number of concurrent batches, from
+    for this workload, tile variant, number of concurrent batches and store
+    kind (write-through or not), from
     profiles/traffic.json (HBM bytes per launch, each counter scaled by what
     it reads for a copy kernel of known size), or None when there is no such
     record or the kernel source has changed since the counters were taken."""
@@ -140,7 +141,7 @@ def measured_traffic(workload, variant_name, batches):
     found = rec.get("entries", {}).get(workload, [])
     for e in (found if isinstance(found, list) else [found]):
         if (isinstance(e, dict) and e.get("variant") == variant_name and e.get("batches") == batches
-                and "bytes_per_launch" in e):
+                and e.get("write_through") == bool(write_through) and "bytes_per_launch" in e):
             return e
     return None
 
@@ -161,6 +162,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-plain", action="store_true")
     ap.add_argument("--variant", type=int, default=-1, help="tile variant; -1 autotunes")
+    ap.add_argument("--write-through", default="auto", choices=["auto", "0", "1"],
+                    help="write-through stores for the one-batch run; auto: the faster, by timing")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-served", action="store_true", help="skip the served-batch latency run")
     ap.add_argument("--tau-nu", type=float, default=0.6, help="tau_nu of the collapse studies")
@@ -508,6 +511,14 @@ def main():
     else:
         variant, _ = batch.autotune(reps=20)
     workload["tile"] = L.variant_names()[variant]
+    # write-through stores for the one-batch run, by timing (they pay where the
+    # populations stay in the caches and cost where they stream from HBM)
+    if args.write_through == "auto":
+        wt1, _ = batch.tune_write_through(reps=20)
+    else:
+        batch.set_write_through(args.write_through == "1")
+        wt1 = batch.write_through
+    workload["write_through_one_batch"] = wt1
     # Independent instances can also be spread over several batches, one
     # stream each, whose kernels then run concurrently (one batch's start-up,
     # tail and kernel boundary overlap another's work); a step is then one
@@ -546,6 +557,7 @@ def main():
         workload["write_through"] = group_wt
         ms, median_ms, nparts = timed_region(torch, L, group, group.streams, args.steps, args.warmup)
     else:
+        workload["write_through"] = wt1
         ms, median_ms, nparts = ms1, median1, nparts1
     for s in sims:
         s.sync()
@@ -594,7 +606,7 @@ def main():
     print("# dominant %s %.4f ms/launch, %.0f GB/s of %d B/site" % (dominant[0], dominant[1], achieved,
                                                                      dominant[2]), file=sys.stderr, flush=True)
 
-    trec = measured_traffic(args.workload, vname, 1)
+    trec = measured_traffic(args.workload, vname, 1, wt1)
     traffic = trec["bytes_per_launch"] if trec else None
     # The MI355X's Infinity Cache (256 MB) sits between the L2s and HBM: a
     # working set that fits it is served from there, and the FETCH_SIZE and
@@ -656,7 +668,7 @@ def main():
         # the sites: the step's algorithmic bytes over the step's time, and
         # the step's measured bytes (launches of a quarter of the grid)
         step_ms = ms / args.steps
-        crec = measured_traffic(args.workload, vname, n_streams)
+        crec = measured_traffic(args.workload, vname, n_streams, group_wt)
         # bytes of one step: every batch's launches in it (a two-step launch
         # counts for two steps)
         c_traffic = round(crec["bytes_per_launch"] * crec["launches_per_step"]) if crec else None

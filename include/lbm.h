@@ -282,15 +282,30 @@ int lbm_resident_blocks(int precision, int variant, int *blocks);
 int lbm_set_variant(void *handle, int variant);
 int lbm_batch_set_variant(void *batch, int variant);
 /* on = 1: the fused single-pass kernel of the 64-column variants ("fused-*")
- * stores the batch's populations with write-through stores (relaxed
+ * and the two-step kernel ("twostep-*", its stores to memory) store the
+ * batch's populations with write-through stores (relaxed
  * agent-scope atomic stores, which leave no dirty line in the XCD's L2);
  * 0 (the default): ordinary stores.  Results are bitwise the same.  Every
  * kernel end writes back the dirty L2 lines of the whole device, so when
  * several batches run concurrently on their own streams (each launch's end
  * then also writes back the others' lines) write-through pays; a batch
- * running alone is faster without it.  The paired and two-pass variants
- * ignore the setting.  LBM_EINVAL for a null batch or on not 0 or 1. */
+ * running alone is faster without it on grids that stream from HBM, and can
+ * be faster with it on grids that stay in the caches
+ * (lbm_batch_tune_write_through decides by timing).  The paired and two-pass
+ * variants ignore the setting.  LBM_EINVAL for a null batch or on not 0 or
+ * 1. */
 int lbm_batch_set_write_through(void *batch, int on);
+/* Times the batch's current variant with write-through stores off and on, in
+ * three passes of min(reps, 8) warm-up steps and reps timed steps each, and
+ * keeps the setting with the fastest pass: *on the setting kept,
+ * *ms_per_step (may be null) its time per step.  For variants that ignore the
+ * setting nothing is timed: *on is the current setting, *ms_per_step NaN.
+ * Which is faster depends on the workload: write-through pays where the
+ * populations stay in the caches (the 24-instance 256 x 256 sweep, also as one
+ * batch with the two-step kernel) and costs where they stream from HBM (an
+ * 8192 x 4096 grid).  It advances the instances' state.  LBM_EINVAL for a
+ * null batch or out pointer or reps < 1, LBM_ESTATE for an empty batch. */
+int lbm_batch_tune_write_through(void *batch, int reps, int *on, float *ms_per_step);
 /* Times every variant on the batch's current instances with HIP events, in
  * three passes of min(reps, 8) warm-up steps and reps timed steps each, scores
  * each variant by its fastest pass, selects the best and returns it with its

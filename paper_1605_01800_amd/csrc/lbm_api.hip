@@ -349,7 +349,7 @@ int enqueue_chunk(int prec, int variant, const InstDev *d_inst, int ninst, const
         // one launch per pair of steps; an instance with an odd count takes
         // its last step alone in launch (n - 1) / 2
         for (int s = 0; s < (K + 1) / 2; ++s)
-            TRYHIP(launch_twostep(prec, variant, d_inst, d_tiles, ntiles, s, st));
+            TRYHIP(launch_twostep(prec, variant, d_inst, d_tiles, ntiles, s, st, write_through));
         TRYHIP(launch_chunk_end(d_inst, ninst, st, d_status, 1));
         return LBM_OK;
     }
@@ -542,7 +542,7 @@ int batch_run(Batch *b, const std::vector<int64_t> &counts, bool timed, float *m
                 if (rc == LBM_OK) {
                     if (pairs)
                         rc = hip_ok(launch_twostep(b->precision, b->variant, b->d_descs, b->d_tiles, b->ntiles, s,
-                                                   b->stream));
+                                                   b->stream, b->write_through));
                     else if (kVariants[b->variant].fused == 2)
                         rc = hip_ok(launch_fused2(b->precision, b->variant, b->d_descs, b->d_tiles, b->ntiles, s, b->stream));
                     else
@@ -1308,6 +1308,49 @@ int lbm_batch_autotune(void *batch, int reps, int *best_variant, float *ms_per_s
     TRY(lbm_batch_set_variant(b, best));
     *best_variant = best;
     if (ms_per_step) *ms_per_step = best_ms / reps;
+    return LBM_OK;
+}
+
+int lbm_batch_tune_write_through(void *batch, int reps, int *on, float *ms_per_step)
+{
+    Batch *b = (Batch *)batch;
+    if (!b || reps < 1 || !on) return LBM_EINVAL;
+    if (b->members.empty()) return LBM_ESTATE;
+    const int kind = kVariants[b->variant].fused;
+    if (kind != 1 && kind != 3) {                // these variants ignore the setting
+        *on = b->write_through;
+        if (ms_per_step) *ms_per_step = NAN;
+        return LBM_OK;
+    }
+    hipEvent_t e0, e1;
+    TRYHIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return LBM_EHIP;
+    }
+    // three passes, each setting scored by its fastest pass, as in autotuning
+    constexpr int kPasses = 3;
+    float score[2] = {INFINITY, INFINITY};
+    int rc = LBM_OK;
+    for (int pass = 0; pass < kPasses && rc == LBM_OK; ++pass) {
+        for (int wt = 0; wt < 2 && rc == LBM_OK; ++wt) {
+            b->write_through = wt;
+            rc = lbm_batch_step(b, std::min(reps, 8));                         // warm-up and capture
+            if (rc == LBM_OK) rc = hip_ok(hipEventRecord(e0, b->stream));
+            if (rc == LBM_OK) rc = lbm_batch_step(b, reps);
+            if (rc == LBM_OK) rc = hip_ok(hipEventRecord(e1, b->stream));
+            if (rc == LBM_OK) rc = hip_ok(hipEventSynchronize(e1));
+            float t = 0.f;
+            if (rc == LBM_OK) rc = hip_ok(hipEventElapsedTime(&t, e0, e1));
+            if (rc == LBM_OK) score[wt] = std::min(score[wt], t);
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->write_through = score[1] < score[0] ? 1 : 0;
+    if (rc != LBM_OK) return rc;
+    *on = b->write_through;
+    if (ms_per_step) *ms_per_step = score[b->write_through] / reps;
     return LBM_OK;
 }
 

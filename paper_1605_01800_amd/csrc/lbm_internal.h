@@ -149,7 +149,7 @@ hipError_t launch_fused2(int prec, int variant, const InstDev *d_inst, const Til
 // Two-step pass s: steps 2s and 2s + 1 of the chunk (only step 2s for an
 // instance whose chunk ends there).
 hipError_t launch_twostep(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles, int ntiles,
-                          int s, hipStream_t st);
+                          int s, hipStream_t st, int write_through);
 hipError_t launch_chunk_end(const InstDev *d_inst, int ninst, hipStream_t st, int *d_status = nullptr,
                             int pairs = 0);
 hipError_t launch_init(int prec, const InstDev *d_inst, int slab_rows, const lbm_bubble *b, int nb,

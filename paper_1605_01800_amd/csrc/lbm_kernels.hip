@@ -1134,7 +1134,8 @@ static_assert(T2_OUT == TWOSTEP_COLS, "two-step strip width");
 
 template <typename T, bool EOS64, int H>
 __global__ __launch_bounds__(BLOCK) void twostep_kernel(const InstDev *__restrict__ insts,
-                                                        const Tile *__restrict__ tiles, int ntiles, int s)
+                                                        const Tile *__restrict__ tiles, int ntiles, int s,
+                                                        int write_through)
 {
     constexpr int RP = 16;
     constexpr int RF = 12;
@@ -1225,7 +1226,10 @@ __global__ __launch_bounds__(BLOCK) void twostep_kernel(const InstDev *__restric
             collide_site<T>(fb, pc, Fx, Fy, R);
             if (single) {
                 // the odd last step of the chunk: straight to memory
-                if (out && c >= tl.y0 && c < y_end) push_store<T>(fo, PB, fb, xo, xeo, xwo, c, ny, RB, walls);
+                if (out && c >= tl.y0 && c < y_end) {
+                    if (write_through) push_store<T, true>(fo, PB, fb, xo, xeo, xwo, c, ny, RB, walls);
+                    else push_store<T>(fo, PB, fb, xo, xeo, xwo, c, ny, RB, walls);
+                }
             } else {
                 // Eq. 5 into the LDS rows of t + 1; halfway bounce-back at walls
                 T *r0 = f1row(c);
@@ -1283,7 +1287,8 @@ __global__ __launch_bounds__(BLOCK) void twostep_kernel(const InstDev *__restric
             T pc, Fx, Fy;
             interaction_force<T>(rS, rC, rN, lane, mG, pc, Fx, Fy);
             collide_site<T>(gb, pc, Fx, Fy, R);
-            push_store<T>(fo, PB, gb, xo, xeo, xwo, cb, ny, RB, walls);
+            if (write_through) push_store<T, true>(fo, PB, gb, xo, xeo, xwo, cb, ny, RB, walls);
+            else push_store<T>(fo, PB, gb, xo, xeo, xwo, cb, ny, RB, walls);
         }
 
         __syncthreads();
@@ -1636,15 +1641,16 @@ hipError_t fused2_dispatch(int variant, const InstDev *di, const Tile *dt, int n
 }
 
 template <typename T, bool E64>
-hipError_t twostep_dispatch(int variant, const InstDev *di, const Tile *dt, int nt, int s, hipStream_t st)
+hipError_t twostep_dispatch(int variant, const InstDev *di, const Tile *dt, int nt, int s, int wt,
+                            hipStream_t st)
 {
     const dim3 grid(grid_for(nt)), block(BLOCK);
     switch (kVariants[variant].rows) {
-    case 16: twostep_kernel<T, E64, 16><<<grid, block, 0, st>>>(di, dt, nt, s); break;
-    case 24: twostep_kernel<T, E64, 24><<<grid, block, 0, st>>>(di, dt, nt, s); break;
-    case 32: twostep_kernel<T, E64, 32><<<grid, block, 0, st>>>(di, dt, nt, s); break;
-    case 48: twostep_kernel<T, E64, 48><<<grid, block, 0, st>>>(di, dt, nt, s); break;
-    case 64: twostep_kernel<T, E64, 64><<<grid, block, 0, st>>>(di, dt, nt, s); break;
+    case 16: twostep_kernel<T, E64, 16><<<grid, block, 0, st>>>(di, dt, nt, s, wt); break;
+    case 24: twostep_kernel<T, E64, 24><<<grid, block, 0, st>>>(di, dt, nt, s, wt); break;
+    case 32: twostep_kernel<T, E64, 32><<<grid, block, 0, st>>>(di, dt, nt, s, wt); break;
+    case 48: twostep_kernel<T, E64, 48><<<grid, block, 0, st>>>(di, dt, nt, s, wt); break;
+    case 64: twostep_kernel<T, E64, 64><<<grid, block, 0, st>>>(di, dt, nt, s, wt); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1780,13 +1786,14 @@ hipError_t launch_fused2(int prec, int variant, const InstDev *d_inst, const Til
 }
 
 hipError_t launch_twostep(int prec, int variant, const InstDev *d_inst, const Tile *d_tiles, int ntiles,
-                          int s, hipStream_t st)
+                          int s, hipStream_t st, int write_through)
 {
     if (ntiles <= 0) return hipSuccess;
     if (kVariants[variant].fused != 3) return hipErrorInvalidValue;
-    if (prec == LBM_FP64) return twostep_dispatch<double, false>(variant, d_inst, d_tiles, ntiles, s, st);
-    if (prec == LBM_FP32) return twostep_dispatch<float, false>(variant, d_inst, d_tiles, ntiles, s, st);
-    return twostep_dispatch<float, true>(variant, d_inst, d_tiles, ntiles, s, st);
+    const int wt = write_through ? 1 : 0;
+    if (prec == LBM_FP64) return twostep_dispatch<double, false>(variant, d_inst, d_tiles, ntiles, s, wt, st);
+    if (prec == LBM_FP32) return twostep_dispatch<float, false>(variant, d_inst, d_tiles, ntiles, s, wt, st);
+    return twostep_dispatch<float, true>(variant, d_inst, d_tiles, ntiles, s, wt, st);
 }
 
 hipError_t launch_chunk_end(const InstDev *d_inst, int ninst, hipStream_t st, int *d_status, int pairs)

@@ -106,6 +106,8 @@ _SIGS = {
     "lbm_batch_destroy": [ctypes.c_void_p],
     "lbm_batch_set_variant": [ctypes.c_void_p, ctypes.c_int],
     "lbm_batch_set_write_through": [ctypes.c_void_p, ctypes.c_int],
+    "lbm_batch_tune_write_through": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_float)],
     "lbm_batch_autotune": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                            ctypes.POINTER(ctypes.c_float)],
     "lbm_variant_count": [],
@@ -444,11 +446,22 @@ class Batch:
         sim._batch = None
 
     def set_write_through(self, on):
-        """Write-through population stores in the fused 64-column kernels:
-        faster when several batches run concurrently, slower alone; results
+        """Write-through population stores in the fused 64-column and the
+        two-step kernels: faster when several batches run concurrently or the
+        grids stay in the caches, slower on grids streamed from HBM; results
         are bitwise the same."""
         _check(lib().lbm_batch_set_write_through(self.b, 1 if on else 0), "lbm_batch_set_write_through")
         self.write_through = bool(on)
+
+    def tune_write_through(self, reps=20):
+        """Times the current variant with write-through stores off and on and
+        keeps the faster setting; returns (on, ms per step or NaN)."""
+        on = ctypes.c_int()
+        ms = ctypes.c_float()
+        _check(lib().lbm_batch_tune_write_through(self.b, int(reps), ctypes.byref(on), ctypes.byref(ms)),
+               "lbm_batch_tune_write_through")
+        self.write_through = bool(on.value)
+        return self.write_through, ms.value
 
     def step(self, n=1):
         _check(lib().lbm_batch_step(self.b, int(n)), "lbm_batch_step")

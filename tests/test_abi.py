@@ -120,6 +120,8 @@ def test_resident_blocks_query_without_a_device():
         assert lib.lbm_resident_blocks(prec, var, ctypes.byref(n)) == -1, (prec, var)
     assert lib.lbm_resident_blocks(0, 0, None) == -1
     assert lib.lbm_batch_set_write_through(None, 1) == -1
+    on = ctypes.c_int(-1)
+    assert lib.lbm_batch_tune_write_through(None, 20, ctypes.byref(on), None) == -1
 
 
 def test_workspace_grows_with_precision_and_grid():

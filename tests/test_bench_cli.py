@@ -26,22 +26,24 @@ def _bench_module():
 def test_traffic_record_matches_workload_variant_and_batches():
     """The committed counter record is for the current kernel source and holds
     one entry per launch shape it was measured in (the benchmark's variants,
-    one batch and four concurrent batches); nothing is reported for a shape
-    or variant it does not hold.  Measured bytes lie between the least a
+    one batch and four concurrent batches, with the stores the benchmark picks
+    for each); nothing is reported for a shape, variant or store kind it does
+    not hold.  Measured bytes lie between the least a
     launch must move (one read and one write of its populations) and 1.3
     times that."""
     b = _bench_module()
-    cases = [("laplace_sweep", "twostep-58x32", 1, 72 * 24 * 256 * 256),
-             ("laplace_sweep", "twostep-58x32", 4, 72 * 6 * 256 * 256),
-             ("collapse_large", "twostep-58x24", 1, 72 * 8192 * 4096)]
-    for wl, v, nb, model in cases:
-        e = b.measured_traffic(wl, v, nb)
-        assert e is not None, (wl, v, nb)
+    cases = [("laplace_sweep", "twostep-58x32", 1, True, 72 * 24 * 256 * 256),
+             ("laplace_sweep", "twostep-58x32", 4, True, 72 * 6 * 256 * 256),
+             ("collapse_large", "twostep-58x24", 1, False, 72 * 8192 * 4096)]
+    for wl, v, nb, wt, model in cases:
+        e = b.measured_traffic(wl, v, nb, wt)
+        assert e is not None, (wl, v, nb, wt)
         assert e["min_hbm_bytes_per_launch"] == model
         assert model <= e["bytes_per_launch"] < 1.3 * model
-    assert b.measured_traffic("laplace_sweep", "twostep-58x32", 2) is None
-    assert b.measured_traffic("laplace_sweep", "fused2-128x16", 1) is None
-    assert b.measured_traffic("single_small", "twostep-58x32", 1) is None
+    assert b.measured_traffic("laplace_sweep", "twostep-58x32", 2, True) is None
+    assert b.measured_traffic("laplace_sweep", "twostep-58x32", 4, False) is None
+    assert b.measured_traffic("laplace_sweep", "fused2-128x16", 1, False) is None
+    assert b.measured_traffic("single_small", "twostep-58x32", 1, False) is None
 
 
 def test_timing_parts_cover_the_steps_in_whole_graphs():

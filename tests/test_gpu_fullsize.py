@@ -205,11 +205,11 @@ def test_batch_group_equals_one_batch_bitwise():
     for n_batches in (1, 4):
         sims = studies.laplace_sweep_sims(L, "fp32", "cuda:0")
         if n_batches == 1:
-            runner = _batch(sims, "fp32", "fused-64x16")
+            runner = _batch(sims, "fp32", "twostep-58x32")
         else:
             runner = L.BatchGroup(sims, precision="fp32", n_batches=n_batches)
             assert runner.batches[0].write_through
-            runner.set_variant(L.variant_names().index("fused-64x16"))
+            runner.set_variant(L.variant_names().index("twostep-58x32"))
         runner.step(300)
         runner.sync()
         out.append([s.populations().cpu().numpy() for s in sims])

@@ -291,10 +291,12 @@ def test_walk_order_does_not_change_results(prec, variant):
 
 
 @pytest.mark.parametrize("prec,variant", [("fp64", "fused-64x16"), ("fp32", "fused-64x32"),
-                                          ("fp32_mixed", "fused-64x16"), ("fp32", "fused2-128x16")])
+                                          ("fp32_mixed", "fused-64x16"), ("fp32", "fused2-128x16"),
+                                          ("fp32", "twostep-58x32"), ("fp64", "twostep-58x24")])
 def test_write_through_stores_do_not_change_results(prec, variant):
     """A batch with write-through population stores steps bitwise like one
-    without (the paired kernels ignore the setting)."""
+    without (the paired kernels ignore the setting), over an odd number of
+    steps, so that a two-step batch also takes its last step alone."""
     T6, T8 = coexist.temperature(0.6), coexist.temperature(0.8)
     specs = [(L.make_params(200, 90, T=T6, walls=True, precision=prec, tau_nu=0.8), [(99.5, 30.0, 20.0)]),
              (L.make_params(78, 129, T=T8, precision=prec, tau_nu=0.51), [(38.0, 64.0, 15.0)])]
@@ -306,7 +308,7 @@ def test_write_through_stores_do_not_change_results(prec, variant):
         batch.set_write_through(wt)
         for s in sims:
             batch.attach(s)
-        batch.step(140)
+        batch.step(141)
         batch.sync()
         out.append([s.populations().cpu() for s in sims])
         batch.close()
