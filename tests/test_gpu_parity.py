@@ -318,6 +318,37 @@ def test_write_through_stores_do_not_change_results(prec, variant):
         assert torch.equal(a, b)
 
 
+def test_write_through_tuning_keeps_a_setting_the_batch_then_uses():
+    """lbm_batch_tune_write_through times a two-step batch both ways and keeps
+    one setting (returned, with a positive time per step); for a paired
+    variant, which ignores the setting, it times nothing and keeps the
+    current one.  Results stay bitwise those of an untuned batch."""
+    p = L.make_params(130, 66, T=coexist.temperature(0.7), walls=True, precision="fp32", tau_nu=0.8)
+    out = []
+    for tune in (False, True):
+        sim = L.Sim(p).init_bubble([(64.5, 30.0, 12.0)], W=4.0)
+        b = L.Batch(precision="fp32", max_instances=1, max_tiles=L.tile_count(p))
+        b.attach(sim)
+        b.set_variant(_variant("twostep-58x24"))
+        if tune:
+            on, ms = b.tune_write_through(reps=4)
+            assert on in (True, False) and on == b.write_through and ms > 0
+            b.set_variant(_variant("fused2-128x16"))
+            b.set_write_through(True)
+            on2, ms2 = b.tune_write_through(reps=4)
+            assert on2 is True and ms2 != ms2                      # NaN: nothing timed
+            b.set_variant(_variant("twostep-58x24"))
+            b.set_write_through(on)
+        else:
+            b.step(3 * 2 * (4 + 4))             # the steps the tuning takes: 3 passes x 2 settings
+        b.step(41)
+        b.sync()
+        out.append(sim.populations().cpu())
+        b.close()
+        sim.close()
+    assert torch.equal(out[0], out[1])
+
+
 def test_paired_variant_rejects_odd_nx():
     p = L.make_params(77, 20, T_over_Tc=0.7, precision="fp32")
     s = L.Sim(p)
