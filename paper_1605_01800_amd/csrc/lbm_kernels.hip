@@ -346,6 +346,58 @@ __global__ __launch_bounds__(BLOCK) void psi_pass_kernel(const InstDev *__restri
 }
 
 // ---------------------------------------------------------------------------
+// stochastic rounding of the binary32 rest population
+// ---------------------------------------------------------------------------
+// lowbias32, the 32-bit integer hash of C. Wellons ("Prospecting for hash
+// functions", 2018): xorshift-multiply rounds with his published constants.
+__device__ __forceinline__ unsigned hash32(unsigned x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// Random words of the stochastic rounding: site (x, y) (0 <= x < nx,
+// 0 <= y < ny) in the step with word hash32(step) draws
+// column_word(x) ^ row_word(y, step word).  Sites that the reflections of
+// the grid through its centre (x -> nx - 1 - x, y -> ny - 1 - y) map onto
+// each other draw the same word, so a mirror-symmetric state stays symmetric
+// bit for bit, as with the mirror-symmetric sums.  The word depends on the
+// instance's own step count and the site alone, not on tiles, batches or
+// kernels, so every kernel family rounds every site alike.  A lane's column
+// word is fixed for a launch and a row's is uniform over a wavefront (one
+// scalar hash per row), so a site pays one exclusive or.
+__device__ __forceinline__ unsigned column_word(int x, int nx)
+{
+    return hash32((unsigned)min(x, nx - 1 - x));
+}
+
+__device__ __forceinline__ unsigned row_word(int y, int ny, unsigned step_word)
+{
+    return hash32((unsigned)min(y, ny - 1 - y) ^ step_word);
+}
+
+// a + b rounded to one of the two binary32 values around it, the farther one
+// with probability (distance to the nearer) / (gap between them), drawn from
+// the top 24 bits of `key`: E[result] = a + b up to 2^-24 of the gap.  An
+// exact sum is returned unchanged.
+__device__ __forceinline__ float stochastic_sum(float a, float b, unsigned key)
+{
+#pragma clang fp contract(off)
+    const float s = a + b;
+    const float bp = s - a;
+    const float err = (a - (s - bp)) + (b - bp);               // a + b = s + err exactly
+    const int step = (err > 0.0f) == (s > 0.0f) ? 1 : -1;      // toward err, in the encoding
+    const float o = __int_as_float(__float_as_int(s) + step);
+    const float gap = fabsf(o - s);
+    const float u = (float)(key >> 8) * 0x1p-24f;
+    return u * gap < fabsf(err) ? o : s;
+}
+
+// ---------------------------------------------------------------------------
 // collision of one site (Eqs. 6, 4, 14, 3 and f* = M^-1 m*)
 // ---------------------------------------------------------------------------
 // f: shifted post-streaming populations g_a = f_a - w_a rho_ref of the site
@@ -362,8 +414,22 @@ __global__ __launch_bounds__(BLOCK) void psi_pass_kernel(const InstDev *__restri
 // vapour) does not pick up the same rounding of its full populations at
 // every site and every step, which in binary32 shifts the mass of a
 // stationary bubble or slab by about 1e-5 over 40,000 steps.
+//
+// Mass of a binary32 site: rounding each of the nine stored populations
+// changes the site's mass by up to half a unit in the last place of each,
+// and in a stationary region the same sites round the same way at every
+// step, so the error grows linearly with the step count (a flat slab, the
+// same in every column, loses or gains mass coherently over all of them).
+// In binary32 the rest population is therefore not formed from its
+// increment: it is the site's pre-collision mass minus the eight stored
+// moving populations, and that sum is rounded to binary32 up or down at
+// random with the probabilities that make the stored value exact on average
+// (stochastic rounding; `key` is the site's random word for this step).  Each site then keeps its mass up to one
+// unbiased rounding of one population, which averages out over sites and
+// steps instead of adding up.  Binary64 storage keeps the increment form.
 template <typename T>
-__device__ __forceinline__ void collide_site(T f[9], T psi_c, T Fx, T Fy, const Consts<T> &R)
+__device__ __forceinline__ void collide_site(T f[9], T psi_c, T Fx, T Fy, const Consts<T> &R,
+                                             unsigned key)
 {
 #pragma clang fp contract(off)
     const T dm = density<T>(f);                 // rho - rho_ref
@@ -429,7 +495,9 @@ __device__ __forceinline__ void collide_site(T f[9], T psi_c, T Fx, T Fy, const 
     const T py = fma(T(-2), d6, d5);
     const T qx = d3 + d4;
     const T qy = d5 + d6;
-    f[0] = fma(T(4), d2 - d1, f[0]);
+    T in[9];
+#pragma unroll
+    for (int a = 1; a < 9; ++a) in[a] = f[a];
     f[1] += ax + px + d7;
     f[2] += ax + py - d7;
     f[3] += ax - px + d7;
@@ -438,6 +506,20 @@ __device__ __forceinline__ void collide_site(T f[9], T psi_c, T Fx, T Fy, const 
     f[6] += dg - qx + qy - d8;
     f[7] += dg - qx - qy + d8;
     f[8] += dg + qx - qy - d8;
+    if constexpr (sizeof(T) == 4) {
+        // f*_0 = f_0 + sum_a (f_a - f*_a): the increment 4 (d2 - d1) plus
+        // every rounding of the eight stores.  Each difference is exact while
+        // the increment is below its population (Dekker) and otherwise both are
+        // tiny; the sum of these small numbers rounds far below the rest
+        // population's last place.  The tree is density()'s.
+        T o[9];
+#pragma unroll
+        for (int a = 1; a < 9; ++a) o[a] = in[a] - f[a];
+        const T moved = ((o[1] + o[3]) + (o[2] + o[4])) + ((o[5] + o[7]) + (o[6] + o[8]));
+        f[0] = stochastic_sum(f[0], moved, key);
+    } else {
+        f[0] = fma(T(4), d2 - d1, f[0]);
+    }
 }
 
 // Eq. 7 at the site in column l of the centre row rC, with the rows below (rS)
@@ -522,6 +604,7 @@ __global__ __launch_bounds__(BLOCK) void collide_stream_kernel(const InstDev *__
     const unsigned long long PB = (unsigned long long)d.plane * sizeof(T);
     const unsigned long long RB = (unsigned long long)d.pitch * sizeof(T);
     const int nx = d.nx, ny = d.ny;
+    const unsigned sw = hash32((unsigned)(d.step + s));
 
     // psi of the tile and a one-site ring; x wraps, y wraps or mirrors at walls
     for (int k = threadIdx.x; k < (TY + 2) * LW; k += BLOCK) {
@@ -548,6 +631,7 @@ __global__ __launch_bounds__(BLOCK) void collide_stream_kernel(const InstDev *__
     const unsigned xo = (unsigned)x * sizeof(T);
     const unsigned xeo = (unsigned)((x + 1 == nx) ? 0 : x + 1) * sizeof(T);
     const unsigned xwo = (unsigned)((x == 0) ? nx - 1 : x - 1) * sizeof(T);
+    const unsigned cw = column_word(x, nx);
 
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
@@ -562,7 +646,7 @@ __global__ __launch_bounds__(BLOCK) void collide_stream_kernel(const InstDev *__
         T pc, Fx, Fy;
         interaction_force<T>(sp + ly * LW, sp + (ly + 1) * LW, sp + (ly + 2) * LW, lx + 1, R.mG, pc,
                              Fx, Fy);
-        collide_site<T>(v, pc, Fx, Fy, R);
+        collide_site<T>(v, pc, Fx, Fy, R, cw ^ row_word(y, ny, sw));
         push_store<T>(fo, PB, v, xo, xeo, xwo, y, ny, RB, d.walls);
     }
 }
@@ -682,6 +766,8 @@ __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict_
     const int w = wave_index();
     const int x = tl.x0 + lane;
     const int xl = x < nx ? x : x % nx;                       // column this lane loads
+    const unsigned sw = hash32((unsigned)(d.step + s));
+    const unsigned cw = column_word(x, nx);
     const unsigned xo = (unsigned)x * sizeof(T), xlo = (unsigned)xl * sizeof(T);
     const unsigned xeo = (unsigned)((x + 1 >= nx) ? 0 : x + 1) * sizeof(T);
     const unsigned xwo = (unsigned)((x == 0) ? nx - 1 : x - 1) * sizeof(T);
@@ -774,7 +860,7 @@ __global__ __launch_bounds__(BLOCK) void fused_kernel(const InstDev *__restrict_
             const T *rN = ring + ((c + 1) & (RING - 1)) * LW;
             T pc, Fx, Fy;
             interaction_force<T>(rS, rC, rN, lane + 1, mG, pc, Fx, Fy);
-            collide_site<T>(fb, pc, Fx, Fy, R);
+            collide_site<T>(fb, pc, Fx, Fy, R, cw ^ row_word(c, ny, sw));
             // write-through stores leave no dirty lines in L2 for the
             // kernel's end to write back (chosen per batch, uniform)
             if (write_through) push_store<T, true>(fo, PB, fb, xo, xeo, xwo, c, ny, RB, walls);
@@ -917,6 +1003,8 @@ __global__ __launch_bounds__(BLOCK) void fused2_kernel(const InstDev *__restrict
     const int lane = threadIdx.x & (TILE_X - 1);
     const int w = wave_index();
     const int cx = tl.x0 + 2 * lane;                         // the pair's first column
+    const unsigned sw = hash32((unsigned)(d.step + s));
+    const unsigned cw0 = column_word(cx, nx), cw1 = column_word(cx + 1, nx);
     const int last_cx = min(tl.x0 + SW, nx) - 2;
     PairLane pl;
     pl.valid = cx < nx;
@@ -1010,9 +1098,10 @@ __global__ __launch_bounds__(BLOCK) void fused2_kernel(const InstDev *__restrict
             }
             T pc, Fx, Fy;
             interaction_force<T>(rS, rC, rN, 2 * lane + 1, mG, pc, Fx, Fy);
-            collide_site<T>(v0, pc, Fx, Fy, R);
+            const unsigned rw = row_word(c, ny, sw);
+            collide_site<T>(v0, pc, Fx, Fy, R, cw0 ^ rw);
             interaction_force<T>(rS, rC, rN, 2 * lane + 2, mG, pc, Fx, Fy);
-            collide_site<T>(v1, pc, Fx, Fy, R);
+            collide_site<T>(v1, pc, Fx, Fy, R, cw1 ^ rw);
 
             // Eq. 5 with halfway bounce-back; the row conditions are uniform
             const bool top = (c == ny - 1), bot = (c == 0);
@@ -1170,6 +1259,9 @@ __global__ __launch_bounds__(BLOCK) void twostep_kernel(const InstDev *__restric
     const unsigned xo = xlo;
     const unsigned xeo = (unsigned)((xl + 1 == nx) ? 0 : xl + 1) * sizeof(T);
     const unsigned xwo = (unsigned)((xl == 0) ? nx - 1 : xl - 1) * sizeof(T);
+    const unsigned swA = hash32((unsigned)(d.step + 2 * s));      // steps t and t + 1
+    const unsigned swB = hash32((unsigned)(d.step + 2 * s + 1));
+    const unsigned cw = column_word(xl, nx);
     const bool lane_a = lane >= 1 && lane <= TILE_X - 2;    // step-t collisions
     const bool lane_b = lane >= 2 && lane <= TILE_X - 3;    // step-t + 1 densities
     const int y_end = min(tl.y0 + H, ny);                   // rows output: [y0, y_end)
@@ -1189,6 +1281,8 @@ __global__ __launch_bounds__(BLOCK) void twostep_kernel(const InstDev *__restric
     auto f1row = [&](int r) { return f1 + ((r + RF) % RF) * (9 * TILE_X); };   // r >= -3
     // loads are issued unconditionally (rows past the last needed one are
     // clamped to it) so that the compiler's wait counts stay exact
+    // returns the memory row, which is also the lattice row of a collided
+    // site (the rows collided at step t lie inside the walls)
     auto load_row = [&](int k, T v[9]) {
         const int l = min(rowA(k), lA_last);
         // rows reach three past the strip, so a periodic grid of fewer than
@@ -1197,11 +1291,13 @@ __global__ __launch_bounds__(BLOCK) void twostep_kernel(const InstDev *__restric
         const gptr<const char> rb = f + (unsigned long long)mr * RB;
 #pragma unroll
         for (int a = 0; a < 9; ++a) v[a] = ld<T>(rb + a * PB, xlo);
+        return mr;
     };
-    load_row(0, fn);
+    // memory rows of fq, fn, fa, fb (uniform over the wavefront)
+    int mq = 0, mn = load_row(0, fn), ma = 0, mb = 0;
 
     auto iteration = [&](int k, bool next) __attribute__((always_inline)) {
-        if (next) load_row(k + 1, fq);
+        if (next) mq = load_row(k + 1, fq);
 
         // step t: rho and psi of the row loaded last
         const int l = rowA(k);
@@ -1223,7 +1319,8 @@ __global__ __launch_bounds__(BLOCK) void twostep_kernel(const InstDev *__restric
             const T *rN = psiA + ((c + 1) & (RP - 1)) * TILE_X;
             T pc, Fx, Fy;
             interaction_force<T>(rS, rC, rN, lane, mG, pc, Fx, Fy);
-            collide_site<T>(fb, pc, Fx, Fy, R);
+            // rows beyond a periodic edge are the wrapped rows' sites
+            collide_site<T>(fb, pc, Fx, Fy, R, cw ^ row_word(mb, ny, swA));
             if (single) {
                 // the odd last step of the chunk: straight to memory
                 if (out && c >= tl.y0 && c < y_end) {
@@ -1286,7 +1383,7 @@ __global__ __launch_bounds__(BLOCK) void twostep_kernel(const InstDev *__restric
             const T *rN = psiB + ((cb + 1) & (RP - 1)) * TILE_X;
             T pc, Fx, Fy;
             interaction_force<T>(rS, rC, rN, lane, mG, pc, Fx, Fy);
-            collide_site<T>(gb, pc, Fx, Fy, R);
+            collide_site<T>(gb, pc, Fx, Fy, R, cw ^ row_word(cb, ny, swB));
             if (write_through) push_store<T, true>(fo, PB, gb, xo, xeo, xwo, cb, ny, RB, walls);
             else push_store<T>(fo, PB, gb, xo, xeo, xwo, cb, ny, RB, walls);
         }
@@ -1300,6 +1397,9 @@ __global__ __launch_bounds__(BLOCK) void twostep_kernel(const InstDev *__restric
             gb[a] = ga[a];
             ga[a] = gn[a];
         }
+        mb = ma;
+        ma = mn;
+        if (next) mn = mq;
     };
 
 #pragma unroll 2

@@ -19,13 +19,12 @@ Tolerances (the binary32 bar): 1e-4 relative on densities (max norm over the
 compared sites, relative to the largest reference density) and on the radius
 history and mass.  Derived quantities take the bound that 1e-4 on the
 densities implies: the pressure jump, |d dp| <= 2 max|dp/drho| 1e-4 rho_max
-over the densities of the run.  Density fields are held to 1e-4 up to the
-horizon where binary32 storage holds it (the sweep's discs to 40,000 steps and
-its slabs to 20,000, the collapse to 10,000); beyond it the largest
-differences sit on interfaces that the binary32 path has moved (the
-collapse's ringing interface; two slabs through a mass drift of about 5e-6), a
-known failure kept as a strict expected failure, so that a change in either
-direction shows.
+over the densities of the run.  The sweep's density fields are held to 1e-4
+over the full 40,000 steps; the collapse's to 10,000 steps.  Beyond that the
+collapse's largest differences sit on its ringing interface, which the
+binary32 path has moved by a few ten-thousandths of a site: a known failure
+kept as a strict expected failure, so that a change in either direction
+shows.
 """
 import os
 
@@ -165,10 +164,6 @@ def test_sweep_disc_density_fields_at_the_horizon(sweep_run):
     assert worst < TOL
 
 
-@pytest.mark.xfail(strict=True, reason="binary32 storage: a slab's state is the same in every column, "
-                                       "so its interfaces round alike in all 256 columns at every step and "
-                                       "its mass drifts by about 5e-6 in 40,000 steps, which moves the "
-                                       "interfaces of two of the four slabs past 1e-4")
 def test_sweep_slab_density_fields_at_the_horizon(sweep_run):
     g, cases, _, _, _, _, snaps = sweep_run
     worst = max(_horizon_errors(g, cases, snaps, slabs=True))
