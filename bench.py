@@ -166,8 +166,10 @@ def parse():
                     help="write-through stores for the one-batch run; auto: the faster, by timing")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-served", action="store_true", help="skip the served-batch latency run")
-    ap.add_argument("--tau-nu", type=float, default=0.6, help="tau_nu of the collapse studies")
-    ap.add_argument("--delta", type=float, default=0.02, help="liquid over-density of the collapse studies")
+    ap.add_argument("--tau-nu", type=float, default=None,
+                    help="tau_nu of the collapse studies (default: the configured one)")
+    ap.add_argument("--delta", type=float, default=None,
+                    help="liquid over-density of the collapse studies (default: the configured one)")
     ap.add_argument("--sigma", type=float, default=0.0111,
                     help="surface tension for the critical-nucleus study (this model's Laplace fit at 0.5 Tc)")
     ap.add_argument("--tau-nu-list", type=float, nargs="+", default=[0.51, 0.6],
@@ -177,12 +179,14 @@ def parse():
     ap.add_argument("--record-every", type=int, default=0, help="record interval of the paper_collapse study")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp32_mixed"],
                     help="precision of the paper_collapse study")
-    ap.add_argument("--served-requests", type=int, default=512)
-    ap.add_argument("--served-budget-gb", type=float, default=8.0)
-    ap.add_argument("--served-batches", type=int, default=2,
+    from paper_1605_01800_amd import inputs
+    c4 = inputs.load_config("c4")
+    ap.add_argument("--served-requests", type=int, default=c4["trace"]["n_requests"])
+    ap.add_argument("--served-budget-gb", type=float, default=c4["serving"]["budget_gb"])
+    ap.add_argument("--served-batches", type=int, default=c4["serving"]["batches"],
                     help="batches (one stream each) the served requests are spread over")
-    ap.add_argument("--served-write-through", type=int, default=1, choices=[0, 1],
-                    help="write-through population stores in the served batches")
+    ap.add_argument("--served-write-through", type=int, default=int(c4["serving"]["write_through"]),
+                    choices=[0, 1], help="write-through population stores in the served batches")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run liblbm's plain copy kernel over MIB MiB, 5 times, and exit "
                          "(reference for the memory-traffic counters)")
@@ -233,13 +237,10 @@ def copy_rate(L, nbytes, stream, reps=50):
 
 
 def collapse_large_sims(L, precision, device):
-    from paper_1605_01800_amd import inputs
-    nx, ny = 8192, 4096
-    bub = inputs.non_overlapping_discs(nx, ny, [300, 200, 150], W=5.0, seed=0, walls=True)
-    p = L.make_params(nx, ny, T_over_Tc=0.6, walls=True, precision=precision, tau_nu=0.6)
-    s = L.Sim(p, device=device)
-    s.init_bubble(bub, W=5.0, delta=0.02)
-    return [s]
+    """The 8192 x 4096 three-disc collapse of configuration c5."""
+    from paper_1605_01800_amd import inputs, studies
+    (inst,) = inputs.config_instances(inputs.load_config("c5"))
+    return [studies.sim_from_instance(L, inst, precision, device)]
 
 
 def collapse_shard_sims(L, precision, device):
@@ -247,14 +248,11 @@ def collapse_shard_sims(L, precision, device):
     lowest 512 rows (lower wall; the cut at the top would exchange a halo
     with the next GPU and is a wall here), with the part of the largest
     disc that falls into them."""
-    from paper_1605_01800_amd import inputs
-    nx, ny = 8192, 4096
-    bub = inputs.non_overlapping_discs(nx, ny, [300, 200, 150], W=5.0, seed=0, walls=True)
-    inside = [b for b in bub if b[1] - b[2] < 512]
-    p = L.make_params(nx, 512, T_over_Tc=0.6, walls=True, precision=precision, tau_nu=0.6)
-    s = L.Sim(p, device=device)
-    s.init_bubble(inside or [(4095.5, 255.5, 150.0)], W=5.0, delta=0.02)
-    return [s]
+    from paper_1605_01800_amd import inputs, studies
+    (inst,) = inputs.config_instances(inputs.load_config("c5"))
+    inside = [b for b in inst["bubbles"] if b[1] - b[2] < 512]
+    shard = dict(inst, ny=512, bubbles=inside or [(4095.5, 255.5, 150.0)])
+    return [studies.sim_from_instance(L, shard, precision, device)]
 
 
 def single_small(device, steps, warmup):
@@ -264,14 +262,15 @@ def single_small(device, steps, warmup):
     captured graphs of 256 steps on the instance's own stream, for each tile
     variant."""
     import torch
+    from paper_1605_01800_amd import inputs, studies
     from paper_1605_01800_amd import lbm as L
-    p = L.make_params(64, 64, T_over_Tc=0.7, precision="fp64", tau_nu=0.8)
-    out = {"metric": "single_instance_mlups", "grid": "64x64", "precision": "fp64", "steps": steps,
-           "variants": {}}
+    cfg = inputs.load_config("c1")
+    (inst,) = inputs.config_instances(cfg)
+    out = {"metric": "single_instance_mlups", "grid": "%dx%d" % (inst["nx"], inst["ny"]),
+           "precision": cfg["precision"], "steps": steps, "variants": {}}
     for v, name in enumerate(L.variant_names()):
-        s = L.Sim(p, device=device)
+        s = studies.sim_from_instance(L, inst, cfg["precision"], device)
         s.set_variant(v)
-        s.init_bubble([(31.5, 31.5, 16.0)], W=2.0)
         s.step(warmup)
         s.sync()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -280,7 +279,7 @@ def single_small(device, steps, warmup):
         e1.record(s.stream)
         e1.synchronize()
         ms = e0.elapsed_time(e1)
-        out["variants"][name] = {"mlups": round(64 * 64 * steps / (ms * 1e-3) / 1e6, 1),
+        out["variants"][name] = {"mlups": round(inst["nx"] * inst["ny"] * steps / (ms * 1e-3) / 1e6, 1),
                                  "us_per_step": round(ms * 1e3 / steps, 3)}
         s.close()
     best = max(out["variants"].items(), key=lambda kv: kv[1]["mlups"])
@@ -359,7 +358,7 @@ def fp64_plain(L, device, steps):
     return len(sims) * 256 * 256 * steps / dt / 1e6
 
 
-def served_run(device, n_requests, budget_gb, load=0.8, chunk=500, seed=0, batches=1, write_through=False):
+def served_run(device, n_requests, budget_gb, load=None, chunk=None, seed=None, batches=1, write_through=False):
     """The served batch: n_requests requests of the served-batch trace (sides
     log-uniform in [64, 1024], aspect 1, 4/3 or 2, half periodic bubbles and
     half wall-bounded collapses, T/Tc in [0.6, 0.9], 5,000-40,000 steps),
@@ -368,11 +367,15 @@ def served_run(device, n_requests, budget_gb, load=0.8, chunk=500, seed=0, batch
     resident requests are spread over `batches` batches on their own streams."""
     import numpy as np
     from paper_1605_01800_amd import inputs, serving
+    c4 = inputs.load_config("c4")
+    load = c4["serving"]["load"] if load is None else load
+    chunk = c4["serving"]["chunk_steps"] if chunk is None else chunk
+    seed = c4["trace"]["seed"] if seed is None else seed
     trace = inputs.request_trace(n_requests, seed)
     reqs0 = serving.make_requests(trace, [0.0] * n_requests)
     be = serving.GpuBackend(precision="fp32", device=device, max_instances=64, max_tiles=1 << 19,
                             n_batches=batches, write_through=write_through)
-    variant, cal_mlups = be.autotune(reqs0[:16])
+    variant, cal_mlups = be.autotune(reqs0[:c4["serving"]["autotune_requests"]])
     work = np.mean([r.sites * r.steps for r in reqs0])
     rate = load * cal_mlups * 1e6 / work
     arrivals = inputs.poisson_arrivals(n_requests, rate, seed + 1)

@@ -1,11 +1,65 @@
 """Seeded synthetic inputs shared by the tests, the benchmark and the serving
-loop.  Holds none of the method's arithmetic: only random layouts, request
-traces and population perturbations, all from numpy generators with fixed
-seeds.
+loop, and the workload configurations (configs/c1 ... c5) they are built
+from.  Holds none of the method's arithmetic: only configurations, random
+layouts, request traces and population perturbations, all from numpy
+generators with fixed seeds.
 """
+import json
 import math
+import os
 
 import numpy as np
+
+CONFIG_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "configs")
+
+
+def load_config(cid):
+    """The workload configuration `cid` ("c1" ... "c5") from
+    configs/<cid>_*.json: grid, boundaries, temperature, initial state, step
+    count and what the run records."""
+    names = [n for n in sorted(os.listdir(CONFIG_DIR)) if n.startswith(cid + "_") and n.endswith(".json")]
+    if len(names) != 1:
+        raise KeyError("no single configuration file for %r in %s" % (cid, CONFIG_DIR))
+    with open(os.path.join(CONFIG_DIR, names[0])) as fh:
+        return json.load(fh)
+
+
+def config_instances(cfg):
+    """The instances of a configuration as plain dicts (nx, ny, walls,
+    T_over_Tc, tau_nu, eps, W, bubbles [(x, y, R)], slab_rows, delta,
+    noise_amp, seed), each the configuration's defaults overridden by its own
+    entries.  A "sweep" expands to the discs of every radius and then one slab
+    at each temperature; "seeded_discs" places discs with
+    non_overlapping_discs."""
+    base = dict(cfg.get("defaults", {}))
+    out = []
+    if "sweep" in cfg:
+        sw = cfg["sweep"]
+        for case in _sweep_cases(sw, sw["nx"]):
+            out.append({**base, "nx": sw["nx"], "ny": sw["ny"], **case})
+    for inst in cfg.get("instances", []):
+        e = {**base, **inst}
+        b = e.get("bubbles", [])
+        if isinstance(b, dict):
+            sd = b["seeded_discs"]
+            e["bubbles"] = non_overlapping_discs(e["nx"], e["ny"], sd["radii"], W=e["W"], seed=sd["seed"],
+                                                 walls=e["walls"])
+        else:
+            e["bubbles"] = [tuple(float(v) for v in x) for x in b]
+        out.append(e)
+    return out
+
+
+def _sweep_cases(sw, n):
+    c = 0.5 * (n - 1)
+    slab = sw["slab_rows"] * n // sw["ny"]
+    cases = []
+    for tr in sw["T_over_Tc"]:
+        for R in sw["radii"]:
+            cases.append({"T_over_Tc": float(tr), "bubbles": [(c, c, float(R))], "slab_rows": 0})
+        cases.append({"T_over_Tc": float(tr), "bubbles": [], "slab_rows": slab})
+    return cases
+
 
 def random_populations(rho, seed, amp=0.3):
     """Populations (ny, nx, 9) whose sum is close to the density field rho:
@@ -45,44 +99,51 @@ def non_overlapping_discs(nx, ny, radii, W, seed, walls=True, max_tries=100000):
 
 
 def laplace_sweep_cases(n=256):
-    """The Laplace-law and coexistence sweep on an n x n periodic grid: discs of
-    radius {20, 30, 40, 50, 60} at T/Tc {0.6, 0.7, 0.8, 0.9} centred on
-    ((n-1)/2, (n-1)/2), plus one flat liquid slab of n/2 rows per temperature."""
-    c = 0.5 * (n - 1)
-    cases = []
-    for tr in (0.6, 0.7, 0.8, 0.9):
-        for R in (20, 30, 40, 50, 60):
-            cases.append({"T_over_Tc": tr, "bubbles": [(c, c, float(R))], "slab_rows": 0})
-        cases.append({"T_over_Tc": tr, "bubbles": [], "slab_rows": n // 2})
-    return cases
+    """The Laplace-law and coexistence sweep of configuration c2 on an n x n
+    periodic grid: discs of every radius at every temperature, centred on
+    ((n-1)/2, (n-1)/2), plus one flat liquid slab (the configured share of the
+    rows) per temperature."""
+    return _sweep_cases(load_config("c2")["sweep"], n)
 
 
-def request_trace(n_requests, seed, side_lo=64, side_hi=1024, steps_lo=5000, steps_hi=40000):
-    """Served-batch requests: sides log-uniform with aspect ratio in {1, 4/3, 2}
+def request_trace(n_requests=None, seed=None, side_lo=None, side_hi=None, steps_lo=None, steps_hi=None):
+    """Served-batch requests of configuration c4 (any argument given overrides
+    it): sides log-uniform with the aspect ratio drawn from the configured set
     (both sides within [side_lo, side_hi]), a 50/50 mix of periodic stationary
-    discs (R = 0.15-0.3 of the short side) and wall-bounded collapses (delta in
-    [0.005, 0.03], centre at a third of the height), T/Tc in [0.6, 0.9], and a
-    step count in [steps_lo, steps_hi].  Arrival times are not included."""
+    discs and wall-bounded collapses (centre at a third of the height), the
+    radius a uniform share of the short side, delta, T/Tc and the step count
+    uniform in their configured ranges.  Arrival times are not included."""
+    tr = load_config("c4")["trace"]
+    n_requests = tr["n_requests"] if n_requests is None else n_requests
+    seed = tr["seed"] if seed is None else seed
+    side_lo = tr["side_lo"] if side_lo is None else side_lo
+    side_hi = tr["side_hi"] if side_hi is None else side_hi
+    steps_lo = tr["steps_lo"] if steps_lo is None else steps_lo
+    steps_hi = tr["steps_hi"] if steps_hi is None else steps_hi
+    aspects = tr["aspects"]
+    t_lo, t_hi = tr["T_over_Tc"]
+    r_lo, r_hi = tr["radius_of_short_side"]
+    d_lo, d_hi = tr["delta"]
     rng = np.random.default_rng(seed)
     out = []
     for k in range(n_requests):
-        aspect = [1.0, 4.0 / 3.0, 2.0][rng.integers(0, 3)]
+        aspect = aspects[rng.integers(0, len(aspects))]
         short = int(round(math.exp(rng.uniform(math.log(side_lo), math.log(side_hi / aspect)))))
         long_ = int(round(aspect * short))
         collapse = bool(rng.integers(0, 2))
-        tr = float(rng.uniform(0.6, 0.9))
+        trr = float(rng.uniform(t_lo, t_hi))
         steps = int(rng.integers(steps_lo, steps_hi + 1))
         if collapse:
             nx, ny = long_, short
-            R = float(rng.uniform(0.15, 0.3)) * short
+            R = float(rng.uniform(r_lo, r_hi)) * short
             y0 = ny / 3.0
             R = min(R, y0 - 6.0)
-            req = {"id": k, "nx": nx, "ny": ny, "walls": True, "T_over_Tc": tr, "steps": steps,
-                   "bubbles": [(0.5 * (nx - 1), y0, R)], "delta": float(rng.uniform(0.005, 0.03))}
+            req = {"id": k, "nx": nx, "ny": ny, "walls": True, "T_over_Tc": trr, "steps": steps,
+                   "bubbles": [(0.5 * (nx - 1), y0, R)], "delta": float(rng.uniform(d_lo, d_hi))}
         else:
             nx, ny = long_, short
-            R = float(rng.uniform(0.15, 0.3)) * short
-            req = {"id": k, "nx": nx, "ny": ny, "walls": False, "T_over_Tc": tr, "steps": steps,
+            R = float(rng.uniform(r_lo, r_hi)) * short
+            req = {"id": k, "nx": nx, "ny": ny, "walls": False, "T_over_Tc": trr, "steps": steps,
                    "bubbles": [(0.5 * (nx - 1), 0.5 * (ny - 1), R)], "delta": 0.0}
         out.append(req)
     return out

@@ -92,32 +92,31 @@ def rel_err_history(h, ref, key, k=None):
 
 
 # ---------------------------------------------------------------------------
-def precision_study(device, large, steps, every, tau_nu=0.6, delta=0.02):
+def precision_study(device, large, steps, every, tau_nu=None, delta=None):
     """The same wall-bounded collapse in binary64, binary32 and binary32 with
     binary64 EOS/psi: MLUPS of each and the relative error of total mass,
-    bubble radii and the wall-pressure peak against binary64."""
+    bubble radii and the wall-pressure peak against binary64.  The grid is the
+    first instance of configuration c5 (large) or c3; tau_nu and delta, when
+    given, replace the configured ones."""
     from . import inputs
     from . import lbm as L
-    if large:
-        nx, ny = 8192, 4096
-        bub = inputs.non_overlapping_discs(nx, ny, [300, 200, 150], W=5.0, seed=0, walls=True)
-        init = dict(bubbles=bub, W=5.0, delta=delta)
-        name = "precision_large"
-    else:
-        nx, ny = 1024, 768
-        bub = [(511.5, 200.0, 120.0)]
-        init = dict(bubbles=bub, W=5.0, delta=delta, noise_amp=1e-3, seed=1)
-        name = "collapse_horizon"
+    inst = inputs.config_instances(inputs.load_config("c5" if large else "c3"))[0]
+    name = "precision_large" if large else "collapse_horizon"
+    nx, ny, bub = inst["nx"], inst["ny"], inst["bubbles"]
+    tau_nu = inst["tau_nu"] if tau_nu is None else tau_nu
+    delta = inst["delta"] if delta is None else delta
+    init = dict(bubbles=bub, W=inst["W"], delta=delta, noise_amp=inst["noise_amp"], seed=inst["seed"])
     runs = {}
     for prec in ("fp64", "fp32", "fp32_mixed"):
-        p = L.make_params(nx, ny, T_over_Tc=0.6, walls=True, precision=prec, tau_nu=tau_nu)
+        p = L.make_params(nx, ny, T_over_Tc=inst["T_over_Tc"], walls=inst["walls"], precision=prec,
+                          tau_nu=tau_nu, eps=inst["eps"])
         hist, mlups, total = run_history(L, p, init, steps, every, device,
                                          variant=L.variant_names().index("fused-64x16"))
         runs[prec] = {"hist": hist, "mlups": mlups}
         _log("%s %s: %.0f MLUPS over %d steps (%.1f s)" % (name, prec, mlups, hist[-1]["step"], total))
     ref = runs["fp64"]["hist"]
-    out = {"metric": name, "grid": "%dx%d" % (nx, ny), "walls_y": True, "T_over_Tc": 0.6, "tau_nu": tau_nu,
-           "eps": 1.86, "delta": delta, "bubbles": [list(b) for b in bub], "steps": steps, "record_every": every,
+    out = {"metric": name, "grid": "%dx%d" % (nx, ny), "walls_y": inst["walls"], "T_over_Tc": inst["T_over_Tc"],
+           "tau_nu": tau_nu, "eps": inst["eps"], "delta": delta, "bubbles": [list(b) for b in bub], "steps": steps, "record_every": every,
            "reference": "binary64 GPU path (within 1e-12 of the FP64 oracle over 10^4 steps)", "runs": {}}
     for prec, r in runs.items():
         h = r["hist"]
@@ -147,15 +146,24 @@ def precision_study(device, large, steps, every, tau_nu=0.6, delta=0.02):
 
 
 # ---------------------------------------------------------------------------
+def sim_from_instance(L, inst, precision, device):
+    """A Sim in the initial state of one configuration instance
+    (inputs.config_instances)."""
+    p = L.make_params(inst["nx"], inst["ny"], T_over_Tc=inst["T_over_Tc"], walls=inst["walls"],
+                      precision=precision, tau_nu=inst["tau_nu"], eps=inst["eps"])
+    s = L.Sim(p, device=device)
+    s.init_bubble(inst["bubbles"], slab_rows=inst.get("slab_rows", 0), W=inst["W"], delta=inst.get("delta", 0.0),
+                  noise_amp=inst.get("noise_amp", 0.0), seed=inst.get("seed", 0))
+    return s
+
+
 def laplace_sweep_sims(L, precision, device, n=256):
+    """The 24 instances of the Laplace-law / coexistence sweep (configuration
+    c2) on n x n grids."""
     from . import inputs
-    sims = []
-    for case in inputs.laplace_sweep_cases(n):
-        p = L.make_params(n, n, T_over_Tc=case["T_over_Tc"], precision=precision, tau_nu=0.6)
-        s = L.Sim(p, device=device)
-        s.init_bubble(case["bubbles"], slab_rows=case["slab_rows"], W=5.0)
-        sims.append(s)
-    return sims
+    base = inputs.load_config("c2")["defaults"]
+    return [sim_from_instance(L, {**base, "nx": n, "ny": n, **case}, precision, device)
+            for case in inputs.laplace_sweep_cases(n)]
 
 
 def _batch_of(L, sims, precision, device, variant="fused-64x16"):
