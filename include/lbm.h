@@ -138,7 +138,14 @@ int lbm_init_density(void *handle, const void *d_rho, double rho_l, double rho_g
 
 /* Enqueues n >= 0 timesteps (Eqs. 15, 13, 7, 6, 4, 14, 3, 5).  Asynchronous.
  * LBM_ESTATE while the handle is attached to a batch (step the batch) or has
- * no state yet; LBM_ENONFINITE once the latch has been read as set. */
+ * no state yet; LBM_ENONFINITE once the latch has been read as set.
+ * Results are deterministic: the same state and step counter give the same
+ * bits with every tile variant, alone or in any batch.  In binary32 the rest
+ * population of every site is rounded stochastically, from a hash of the
+ * site and the step counter, so that each site keeps its mass on average;
+ * a state restored with its step counter (lbm_load) therefore steps
+ * bitwise as the original, while lbm_set_populations (which resets the
+ * counter) may differ from it in the last bits. */
 int lbm_step(void *handle, int64_t n);
 
 /* Macroscopic fields of the current state and the diagnostics.  d_rho, d_ux,
