@@ -125,15 +125,19 @@ def measured_traffic(workload, variant_name, batches, write_through):
     kind (write-through or not), from
     profiles/traffic.json (HBM bytes per launch, each counter scaled by what
     it reads for a copy kernel of known size), or None when there is no such
-    record or the kernel source has changed since the counters were taken."""
+    record or the kernel source (lbm_kernels.hip and lbm_rounding.h) has
+    changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    src = os.path.join(ROOT, "paper_1605_01800_amd", "csrc", "lbm_kernels.hip")
+    csrc = os.path.join(ROOT, "paper_1605_01800_amd", "csrc")
     try:
         with open(path) as fh:
             rec = json.load(fh)
-        with open(src, "rb") as fh:
-            sha = hashlib.sha256(fh.read()).hexdigest()
+        h = hashlib.sha256()
+        for name in ("lbm_kernels.hip", "lbm_rounding.h"):    # the kernels' device code
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(fh.read())
+        sha = h.hexdigest()
     except (OSError, ValueError):
         return None
     if not isinstance(rec, dict) or rec.get("kernels_source_sha256") != sha:

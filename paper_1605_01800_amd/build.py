@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "_lib", "liblbm.so")
 SOURCES = ["lbm_kernels.hip", "lbm_api.hip", "lbm_eos.cpp"]
-HEADERS = ["lbm_internal.h", os.path.join(ROOT, "include", "lbm.h")]
+HEADERS = ["lbm_internal.h", "lbm_rounding.h", os.path.join(ROOT, "include", "lbm.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -24,6 +24,7 @@
 #include <mutex>
 
 #include "lbm_internal.h"
+#include "lbm_rounding.h"
 
 namespace lbm {
 
@@ -343,58 +344,6 @@ __global__ __launch_bounds__(BLOCK) void psi_pass_kernel(const InstDev *__restri
         if (threadIdx.x == 0 && red[0] > -INFINITY)
             atomicMax(&d.wall_keys[s], order_key(red[0]));
     }
-}
-
-// ---------------------------------------------------------------------------
-// stochastic rounding of the binary32 rest population
-// ---------------------------------------------------------------------------
-// lowbias32, the 32-bit integer hash of C. Wellons ("Prospecting for hash
-// functions", 2018): xorshift-multiply rounds with his published constants.
-__device__ __forceinline__ unsigned hash32(unsigned x)
-{
-    x ^= x >> 16;
-    x *= 0x7feb352du;
-    x ^= x >> 15;
-    x *= 0x846ca68bu;
-    x ^= x >> 16;
-    return x;
-}
-
-// Random words of the stochastic rounding: site (x, y) (0 <= x < nx,
-// 0 <= y < ny) in the step with word hash32(step) draws
-// column_word(x) ^ row_word(y, step word).  Sites that the reflections of
-// the grid through its centre (x -> nx - 1 - x, y -> ny - 1 - y) map onto
-// each other draw the same word, so a mirror-symmetric state stays symmetric
-// bit for bit, as with the mirror-symmetric sums.  The word depends on the
-// instance's own step count and the site alone, not on tiles, batches or
-// kernels, so every kernel family rounds every site alike.  A lane's column
-// word is fixed for a launch and a row's is uniform over a wavefront (one
-// scalar hash per row), so a site pays one exclusive or.
-__device__ __forceinline__ unsigned column_word(int x, int nx)
-{
-    return hash32((unsigned)min(x, nx - 1 - x));
-}
-
-__device__ __forceinline__ unsigned row_word(int y, int ny, unsigned step_word)
-{
-    return hash32((unsigned)min(y, ny - 1 - y) ^ step_word);
-}
-
-// a + b rounded to one of the two binary32 values around it, the farther one
-// with probability (distance to the nearer) / (gap between them), drawn from
-// the top 24 bits of `key`: E[result] = a + b up to 2^-24 of the gap.  An
-// exact sum is returned unchanged.
-__device__ __forceinline__ float stochastic_sum(float a, float b, unsigned key)
-{
-#pragma clang fp contract(off)
-    const float s = a + b;
-    const float bp = s - a;
-    const float err = (a - (s - bp)) + (b - bp);               // a + b = s + err exactly
-    const int step = (err > 0.0f) == (s > 0.0f) ? 1 : -1;      // toward err, in the encoding
-    const float o = __int_as_float(__float_as_int(s) + step);
-    const float gap = fabsf(o - s);
-    const float u = (float)(key >> 8) * 0x1p-24f;
-    return u * gap < fabsf(err) ? o : s;
 }
 
 // ---------------------------------------------------------------------------
