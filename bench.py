@@ -1,11 +1,11 @@
 """Benchmark of the D2Q9 pseudopotential MRT lattice Boltzmann timestep on one
 MI355X.
 
-Default workload: the Laplace-law and coexistence sweep (24 instances of a
-256 x 256 periodic grid: discs of radius 20..60 at T/Tc 0.6..0.9 plus one liquid
-slab per temperature), binary32, with the tile variant the autotuner picks
-(normally the fused single-pass kernel: one launch per step), replayed from
-captured HIP graphs.  A "step" advances all 24 instances by one timestep.  The
+Default workload: the Laplace-law and coexistence sweep (configuration c2: 24
+instances of a 256 x 256 periodic grid, discs of radius 20..60 at T/Tc
+0.6..0.9 plus one liquid slab per temperature), binary32, with the tile variant
+the autotuner picks (normally the two-step kernel: one launch per two steps),
+replayed from captured HIP graphs.  A "step" advances all 24 instances by one timestep.  The
 steps are timed twice: as one batch over the tiles of all 24 instances on one
 stream (one launch per step over every site), then spread over four batches on
 four streams whose launches run concurrently, with write-through population
@@ -20,9 +20,11 @@ oracle's CPU rate on
 a bounded sample, the plain per-instance binary64 rate (one instance at a time,
 direct launches, no graph, no batch) and the served-batch latencies.
 
-Other workloads: collapse_large (one 8192 x 4096 wall-bounded grid, HBM
-resident) and the experiment drivers of paper_1605_01800_amd.studies, each
-printing its own JSON line.
+Other workloads: collapse_large (configuration c5: one 8192 x 4096
+wall-bounded grid, HBM resident), single_small (c1) and the experiment drivers
+of paper_1605_01800_amd.studies, each printing its own JSON line.  The served
+batch follows configuration c4.  The configurations are the JSON files of
+paper_1605_01800_amd/configs.
 """
 import argparse
 import json
