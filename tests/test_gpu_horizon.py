@@ -252,6 +252,22 @@ def test_collapse_density_field_early(collapse_run, step):
     assert e < TOL
 
 
+@pytest.mark.parametrize("step", [1000, 5000, 10000, 20000, 50000])
+def test_collapse_density_field_in_the_mean(collapse_run, step):
+    """Over the whole horizon the binary32 field agrees with the oracle's to
+    1e-4 in the relative L2 norm over the sampled sites (every fourth site of
+    the grid): the differences beyond 10,000 steps that fail the max norm
+    (test_collapse_density_field_late) are confined to the ringing
+    interface."""
+    g, _, _, snaps, _ = collapse_run
+    j = [int(s) for s in g["snap_steps"]].index(step)
+    ref = g["snaps"][j].astype(np.float64)
+    got = snaps[step][::4, ::4]
+    e = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print("density field at step %d: relative L2 err %.2e" % (step, e), flush=True)
+    assert e < TOL
+
+
 @pytest.mark.xfail(strict=True, reason="binary32 storage: the ringing interface drifts past 1e-4 "
                                        "of the density range after about 10,000 steps")
 @pytest.mark.parametrize("step", [20000, 50000])
