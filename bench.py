@@ -494,21 +494,29 @@ def main():
         return
     precision = "fp32"
     es = 4
+    from paper_1605_01800_amd import inputs
     if args.workload == "laplace_sweep":
         sims = studies.laplace_sweep_sims(L, precision, device)
-        workload = {"workload": "laplace_sweep", "instances": len(sims), "grid": "256x256",
-                    "periodic": True, "T_over_Tc": [0.6, 0.7, 0.8, 0.9], "radii": [20, 30, 40, 50, 60],
-                    "slab_rows": 128, "tau_nu": 0.6, "eps": 1.86}
-    elif args.workload == "collapse_shard":
-        sims = collapse_shard_sims(L, precision, device)
-        workload = {"workload": "collapse_shard", "instances": 1, "grid": "8192x512",
-                    "shard_of": "8192x4096 over 8 GPUs (rows 0-511, lower wall)", "walls_y": True,
-                    "T_over_Tc": 0.6, "delta": 0.02, "tau_nu": 0.6, "eps": 1.86}
+        cfg = inputs.load_config("c2")
+        sw, d = cfg["sweep"], cfg["defaults"]
+        workload = {"workload": "laplace_sweep", "configuration": "c2", "instances": len(sims),
+                    "grid": "%dx%d" % (sw["nx"], sw["ny"]), "periodic": not d["walls"],
+                    "T_over_Tc": sw["T_over_Tc"], "radii": sw["radii"], "slab_rows": sw["slab_rows"],
+                    "tau_nu": d["tau_nu"], "eps": d["eps"]}
     else:
-        sims = collapse_large_sims(L, precision, device)
-        workload = {"workload": "collapse_large", "instances": 1, "grid": "8192x4096",
-                    "walls_y": True, "T_over_Tc": 0.6, "radii": [300, 200, 150], "delta": 0.02,
-                    "tau_nu": 0.6, "eps": 1.86}
+        (inst,) = inputs.config_instances(inputs.load_config("c5"))
+        common = {"instances": 1, "walls_y": inst["walls"], "T_over_Tc": inst["T_over_Tc"],
+                  "delta": inst["delta"], "tau_nu": inst["tau_nu"], "eps": inst["eps"]}
+        if args.workload == "collapse_shard":
+            sims = collapse_shard_sims(L, precision, device)
+            workload = {"workload": "collapse_shard", "configuration": "c5", "grid": "%dx512" % inst["nx"],
+                        "shard_of": "%dx%d over 8 GPUs (rows 0-511, lower wall)" % (inst["nx"], inst["ny"]),
+                        **common}
+        else:
+            sims = collapse_large_sims(L, precision, device)
+            workload = {"workload": "collapse_large", "configuration": "c5",
+                        "grid": "%dx%d" % (inst["nx"], inst["ny"]),
+                        "radii": [b[2] for b in inst["bubbles"]], **common}
     sites = sum(s.nx * s.ny for s in sims)
     max_tiles = sum(L.tile_count(s.params) for s in sims)
     batch = L.Batch(precision=precision, max_instances=len(sims), max_tiles=max_tiles, device=device)

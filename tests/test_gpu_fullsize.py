@@ -228,17 +228,24 @@ def test_batch_group_equals_one_batch_bitwise():
 
 
 def test_precision_study_large_grid_reduced_steps():
-    """The 8192 x 4096 three-disc collapse (T = 0.6 T_c, delta = 0.02, tau_nu =
-    0.6) over its first 2000 steps in binary32 and in binary32 with binary64
-    EOS and psi near the spinodal, against the binary64 GPU path (held to the
-    oracle at 1e-12): total mass, every bubble's radius history and the
-    wall-pressure peak within 1e-4."""
+    """The 8192 x 4096 three-disc collapse (configuration c5: T = 0.6 T_c,
+    delta = 0.02, tau_nu = 0.6) over its first 6000 steps, which include the
+    wall-pressure peak (step 5297) and end before the first bubble vanishes
+    completely (the model then leaves the range where Eq. 13 gives a real
+    psi, near step 6400), in binary32 and in binary32 with binary64 EOS and
+    psi near the spinodal, against the binary64 GPU path (held to the oracle
+    at 1e-12): total mass, every bubble's radius history and the wall-pressure
+    peak within 1e-4, the peak at the same step."""
     print("case precision large", flush=True)
-    out = studies.precision_study("cuda:0", True, steps=2000, every=250)
+    out = studies.precision_study("cuda:0", True, steps=6000, every=300)
+    ref = out["runs"]["fp64"]
+    assert not ref["nonfinite"] and ref["steps_done"] == 6000
     for prec in ("fp32", "fp32_mixed"):
         e = out["runs"][prec]
-        print(prec, e["mass_max_rel_err"], e["radius_max_rel_err"], e.get("wall_p_max_rel_err"), flush=True)
-        assert not e["nonfinite"] and e["steps_done"] == 2000
+        print(prec, e["mass_max_rel_err"], e["radius_max_rel_err"], e.get("wall_p_max_rel_err"),
+              e.get("wall_p_step"), ref["wall_p_step"], flush=True)
+        assert not e["nonfinite"] and e["steps_done"] == 6000
         assert e["mass_max_rel_err"] < 1e-4
         assert max(e["radius_max_rel_err"]) < 1e-4
         assert e["wall_p_max_rel_err"] < 1e-4
+        assert e["wall_p_step"] == ref["wall_p_step"]
