@@ -373,9 +373,10 @@ __global__ __launch_bounds__(BLOCK) void psi_pass_kernel(const InstDev *__restri
 // increment: it is the site's pre-collision mass minus the eight stored
 // moving populations, and that sum is rounded to binary32 up or down at
 // random with the probabilities that make the stored value exact on average
-// (stochastic rounding; `key` is the site's random word for this step).  Each site then keeps its mass up to one
-// unbiased rounding of one population, which averages out over sites and
-// steps instead of adding up.  Binary64 storage keeps the increment form.
+// (stochastic rounding, lbm_rounding.h; `key` is the site's random word for
+// this step).  Each site then keeps its mass up to one unbiased rounding of
+// one population, which averages out over sites and steps instead of adding
+// up.  Binary64 storage keeps the increment form.
 template <typename T>
 __device__ __forceinline__ void collide_site(T f[9], T psi_c, T Fx, T Fy, const Consts<T> &R,
                                              unsigned key)
