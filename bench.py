@@ -152,6 +152,29 @@ def measured_traffic(workload, variant_name, batches, write_through):
     return None
 
 
+# Vector-ALU issue peak of the MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz,
+# one lane-operation per lane and clock (a wave64 instruction issues over four
+# clocks; no packed or dual-issued forms, which the build switches off):
+# 39.3 T lane-operations/s, the fp32 vector peak of 157.3 TFLOP/s counted as
+# one lane-operation per fused multiply-add and without packing.
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def valu_roofline(rec, launch_ms, site_updates):
+    """The launch against the vector-ALU issue peak, from the SQ_INSTS_VALU
+    count in the counter record (wave instructions per launch, x 64 lanes),
+    or None without such a record."""
+    if not rec or "valu_insts_per_launch" not in rec:
+        return None
+    lane_slots = rec["valu_insts_per_launch"] * 64
+    achieved = lane_slots / (launch_ms * 1e-3)
+    return {"bound": "alu", "achieved": round(achieved / 1e12, 2), "peak": round(VALU_PEAK_LANE_OPS / 1e12, 2),
+            "unit": "T lane-ops/s", "frac": round(achieved / VALU_PEAK_LANE_OPS, 4),
+            "valu_insts_per_launch": rec["valu_insts_per_launch"],
+            "lane_slots_per_site_update": round(lane_slots / site_updates, 1),
+            "issue_floor_ms": round(lane_slots / VALU_PEAK_LANE_OPS * 1e3, 5)}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -677,6 +700,7 @@ def main():
             # reach on this part, launch cost included
             "copy_same_bytes_GB_s": round(copy_gbs, 1),
             "frac_of_copy": round(min_hbm_gbs / copy_gbs, 4),
+            "valu": valu_roofline(trec, dominant[1], sites * spl),
         },
         "kernels": kernels,
     }

@@ -40,6 +40,11 @@ def test_traffic_record_matches_workload_variant_and_batches():
         assert e is not None, (wl, v, nb, wt)
         assert e["min_hbm_bytes_per_launch"] == model
         assert model <= e["bytes_per_launch"] < 1.3 * model
+    for wl, v, nb, wt, sites in (("laplace_sweep", "twostep-58x32", 1, True, 24 * 256 * 256),
+                                 ("collapse_large", "twostep-58x24", 1, False, 8192 * 4096)):
+        r = b.valu_roofline(b.measured_traffic(wl, v, nb, wt), 1.0, 2 * sites)
+        assert r is not None and r["bound"] == "alu" and 150 < r["lane_slots_per_site_update"] < 600
+    assert b.valu_roofline(None, 1.0, 1) is None
     assert b.measured_traffic("laplace_sweep", "twostep-58x32", 2, True) is None
     assert b.measured_traffic("laplace_sweep", "twostep-58x32", 4, False) is None
     assert b.measured_traffic("laplace_sweep", "fused2-128x16", 1, False) is None
