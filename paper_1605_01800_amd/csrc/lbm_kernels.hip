@@ -1236,8 +1236,16 @@ __global__ __launch_bounds__(BLOCK) void twostep_kernel(const InstDev *__restric
     auto load_row = [&](int k, T v[9]) {
         const int l = min(rowA(k), lA_last);
         // rows reach three past the strip, so a periodic grid of fewer than
-        // three rows wraps more than once: a full modulo
-        const int mr = walls ? min(max(l, 0), ny - 1) : ((l % ny) + ny) % ny;
+        // three rows wraps more than once; the row is uniform over the
+        // wavefront, and these loops (at most one pass on three rows or more)
+        // run on the scalar unit, where a modulo would take a vector division
+        int mr = l;
+        if (walls) {
+            mr = min(max(l, 0), ny - 1);
+        } else {
+            while (mr < 0) mr += ny;
+            while (mr >= ny) mr -= ny;
+        }
         const gptr<const char> rb = f + (unsigned long long)mr * RB;
 #pragma unroll
         for (int a = 0; a < 9; ++a) v[a] = ld<T>(rb + a * PB, xlo);
