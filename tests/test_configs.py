@@ -47,21 +47,21 @@ def test_c2_expands_to_the_24_sweep_instances_of_the_oracle_reference():
     assert np.array_equal(np.nan_to_num(g["R"]), radii)
 
 
-def test_c3_first_instance_is_the_oracle_reference_collapse():
+def test_c3_instances_are_the_oracle_reference_collapses():
     cfg = inputs.load_config("c3")
     inst = inputs.config_instances(cfg)
-    assert [i["delta"] for i in inst] == [0.02, 0.01]
-    i = inst[0]
-    assert (i["nx"], i["ny"], i["walls"], i["T_over_Tc"]) == (1024, 768, True, 0.6)
-    path = os.path.join(GOLDEN, "collapse_1024x768_50k_d020_s1.npz")
-    if not os.path.exists(path):
-        pytest.skip("oracle reference not generated")
-    g = np.load(path, allow_pickle=False)
-    assert int(g["steps"]) == cfg["steps"] and int(g["every"]) == cfg["record_every"]
-    assert float(g["delta"]) == i["delta"] and int(g["seed"]) == i["seed"]
-    assert float(g["noise_amp"]) == i["noise_amp"] and float(g["W"]) == i["W"]
-    assert float(g["tau_nu"]) == i["tau_nu"] and float(g["T_over_Tc"]) == i["T_over_Tc"]
-    assert tuple(float(v) for v in g["bubble"]) == i["bubbles"][0]
+    assert [(i["delta"], i["seed"]) for i in inst] == [(0.02, 1), (0.01, 2)]
+    for i in inst:
+        assert (i["nx"], i["ny"], i["walls"], i["T_over_Tc"]) == (1024, 768, True, 0.6)
+        path = os.path.join(GOLDEN, "collapse_1024x768_50k_d%03d_s%d.npz" % (round(i["delta"] * 1000), i["seed"]))
+        if not os.path.exists(path):
+            pytest.skip("oracle reference %s not generated" % os.path.basename(path))
+        g = np.load(path, allow_pickle=False)
+        assert int(g["steps"]) == cfg["steps"] and int(g["every"]) == cfg["record_every"]
+        assert float(g["delta"]) == i["delta"] and int(g["seed"]) == i["seed"]
+        assert float(g["noise_amp"]) == i["noise_amp"] and float(g["W"]) == i["W"]
+        assert float(g["tau_nu"]) == i["tau_nu"] and float(g["T_over_Tc"]) == i["T_over_Tc"]
+        assert tuple(float(v) for v in g["bubble"]) == i["bubbles"][0]
 
 
 def test_c4_trace_follows_its_configuration():

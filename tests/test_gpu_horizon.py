@@ -40,7 +40,11 @@ from paper_1605_01800_amd import inputs  # noqa: E402
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 SWEEP = os.path.join(GOLDEN, "laplace_sweep_40k.npz")
-COLLAPSE = os.path.join(GOLDEN, "collapse_1024x768_50k_d020_s1.npz")
+# the two instances of the collapse configuration (delta, noise seed)
+COLLAPSES = {"d020_s1": os.path.join(GOLDEN, "collapse_1024x768_50k_d020_s1.npz"),
+             "d010_s2": os.path.join(GOLDEN, "collapse_1024x768_50k_d010_s2.npz")}
+# whether the binary32 field holds 1e-4 in the max norm past 10,000 steps
+LATE_MAX_NORM_HOLDS = {"d020_s1": False, "d010_s2": False}
 TOL = 1e-4
 
 
@@ -194,9 +198,9 @@ def test_sweep_pressure_jumps_and_slab_densities(sweep_run):
             assert abs(ls - g["slab_rho_l"][i]) / scale < TOL
 
 
-@pytest.fixture(scope="module")
-def collapse_run():
-    g = _load(COLLAPSE)
+@pytest.fixture(scope="module", params=sorted(COLLAPSES))
+def collapse_run(request):
+    g = _load(COLLAPSES[request.param])
     steps, every = int(g["steps"]), int(g["every"])
     nx, ny = 1024, 768
     p = L.make_params(nx, ny, T=float(g["T"]), walls=True, precision="fp32", tau_nu=float(g["tau_nu"]))
@@ -222,11 +226,11 @@ def collapse_run():
     d = sim.diag()
     b.close()
     sim.close()
-    return g, radius, mass, snaps, d
+    return g, radius, mass, snaps, d, request.param
 
 
 def test_collapse_radius_mass_and_wall_peak(collapse_run):
-    g, radius, mass, _, d = collapse_run
+    g, radius, mass, _, d, _ = collapse_run
     er = np.max(np.abs(radius - g["radius"]) / g["radius"])
     em = np.max(np.abs(mass - g["mass"]) / g["mass"])
     ew = abs(d["wall_p_max"] - float(g["wall_p_max"])) / abs(float(g["wall_p_max"]))
@@ -246,7 +250,7 @@ def _snapshot_err(g, snaps, step):
 
 @pytest.mark.parametrize("step", [1000, 5000, 10000])
 def test_collapse_density_field_early(collapse_run, step):
-    g, _, _, snaps, _ = collapse_run
+    g, _, _, snaps, _, _ = collapse_run
     e = _snapshot_err(g, snaps, step)
     print("density field at step %d: max rel err %.2e" % (step, e), flush=True)
     assert e < TOL
@@ -259,7 +263,7 @@ def test_collapse_density_field_in_the_mean(collapse_run, step):
     the grid): the differences beyond 10,000 steps that fail the max norm
     (test_collapse_density_field_late) are confined to the ringing
     interface."""
-    g, _, _, snaps, _ = collapse_run
+    g, _, _, snaps, _, _ = collapse_run
     j = [int(s) for s in g["snap_steps"]].index(step)
     ref = g["snaps"][j].astype(np.float64)
     got = snaps[step][::4, ::4]
@@ -268,17 +272,20 @@ def test_collapse_density_field_in_the_mean(collapse_run, step):
     assert e < TOL
 
 
-@pytest.mark.xfail(strict=True, reason="binary32 storage: the ringing interface drifts past 1e-4 "
-                                       "of the density range after about 10,000 steps")
 @pytest.mark.parametrize("step", [20000, 50000])
-def test_collapse_density_field_late(collapse_run, step):
-    g, _, _, snaps, _ = collapse_run
+def test_collapse_density_field_late(request, collapse_run, step):
+    g, _, _, snaps, _, case = collapse_run
+    if not LATE_MAX_NORM_HOLDS[case]:
+        request.applymarker(pytest.mark.xfail(
+            strict=True, reason="binary32 storage: the ringing interface drifts past 1e-4 of the "
+                                "density range after about 10,000 steps"))
     e = _snapshot_err(g, snaps, step)
     print("density field at step %d: max rel err %.2e" % (step, e), flush=True)
     assert e < TOL
 
 
-def test_collapse_binary64_follows_the_oracle_over_the_whole_horizon():
+@pytest.mark.parametrize("case", sorted(COLLAPSES))
+def test_collapse_binary64_follows_the_oracle_over_the_whole_horizon(case):
     """The same 50,000-step collapse in binary64 (the fused single-step
     kernel) against the oracle's run: the flow amplifies the two programs'
     different rounding orders (unit roundoff 1.1e-16) by about 10^6 over the
@@ -288,7 +295,7 @@ def test_collapse_binary64_follows_the_oracle_over_the_whole_horizon():
     orders of magnitude inside the binary32 bar where binary32 leaves it
     (test_collapse_density_field_late): that failure is the storage
     precision's, not a difference of model or path."""
-    g = _load(COLLAPSE)
+    g = _load(COLLAPSES[case])
     steps, every = int(g["steps"]), int(g["every"])
     p = L.make_params(1024, 768, T=float(g["T"]), walls=True, precision="fp64", tau_nu=float(g["tau_nu"]))
     sim = L.Sim(p)
