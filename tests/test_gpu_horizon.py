@@ -8,9 +8,10 @@ come from tests/golden/make_horizon_goldens.py (which calls only oracle/):
     snapshots at 10,000, 20,000 and 40,000 steps (every fourth site, plus the
     full row and column through the centre), the final pressure jump of every
     disc and the coexisting densities of every slab;
-  * the 1024 x 768 wall-bounded collapse (50,000 steps) as one batch with the
-    two-step kernel: radius and mass every 100 steps, the wall-pressure peak
-    and its step, and density snapshots.
+  * the 1024 x 768 wall-bounded collapse (50,000 steps, both instances of its
+    configuration) as one batch with the two-step kernel: radius and mass
+    every 100 steps, the wall-pressure peak and its step, and density
+    snapshots.
 
 (The single-step and two-step kernels step bitwise alike, so the choice
 among them does not change these results.)
@@ -20,11 +21,13 @@ compared sites, relative to the largest reference density) and on the radius
 history and mass.  Derived quantities take the bound that 1e-4 on the
 densities implies: the pressure jump, |d dp| <= 2 max|dp/drho| 1e-4 rho_max
 over the densities of the run.  The sweep's density fields are held to 1e-4
-over the full 40,000 steps; the collapse's to 10,000 steps.  Beyond that the
-collapse's largest differences sit on its ringing interface, which the
-binary32 path has moved by a few ten-thousandths of a site: a known failure
-kept as a strict expected failure, so that a change in either direction
-shows.
+over the full 40,000 steps; the collapse's (both instances of its
+configuration: delta 0.02 with noise seed 1, delta 0.01 with seed 2) to
+10,000 steps in the max norm and over all 50,000 in the relative L2 norm.
+Beyond 10,000 steps the collapse's largest differences sit on its ringing
+interface, which the binary32 path has moved by about a thousandth of a site:
+where that passes 1e-4 it is a known failure, kept as a strict expected
+failure, so that a change in either direction shows.
 """
 import os
 
@@ -44,7 +47,10 @@ SWEEP = os.path.join(GOLDEN, "laplace_sweep_40k.npz")
 COLLAPSES = {"d020_s1": os.path.join(GOLDEN, "collapse_1024x768_50k_d020_s1.npz"),
              "d010_s2": os.path.join(GOLDEN, "collapse_1024x768_50k_d010_s2.npz")}
 # whether the binary32 field holds 1e-4 in the max norm past 10,000 steps
-LATE_MAX_NORM_HOLDS = {"d020_s1": False, "d010_s2": False}
+# (measured: delta 0.02 1.7e-4 and 2.6e-4 at 20,000 and 50,000 steps, delta
+# 0.01 4.8e-5 and 1.2e-4)
+LATE_MAX_NORM_HOLDS = {("d020_s1", 20000): False, ("d020_s1", 50000): False,
+                       ("d010_s2", 20000): True, ("d010_s2", 50000): False}
 TOL = 1e-4
 
 
@@ -275,7 +281,7 @@ def test_collapse_density_field_in_the_mean(collapse_run, step):
 @pytest.mark.parametrize("step", [20000, 50000])
 def test_collapse_density_field_late(request, collapse_run, step):
     g, _, _, snaps, _, case = collapse_run
-    if not LATE_MAX_NORM_HOLDS[case]:
+    if not LATE_MAX_NORM_HOLDS[(case, step)]:
         request.applymarker(pytest.mark.xfail(
             strict=True, reason="binary32 storage: the ringing interface drifts past 1e-4 of the "
                                 "density range after about 10,000 steps"))
@@ -286,13 +292,14 @@ def test_collapse_density_field_late(request, collapse_run, step):
 
 @pytest.mark.parametrize("case", sorted(COLLAPSES))
 def test_collapse_binary64_follows_the_oracle_over_the_whole_horizon(case):
-    """The same 50,000-step collapse in binary64 (the fused single-step
-    kernel) against the oracle's run: the flow amplifies the two programs'
-    different rounding orders (unit roundoff 1.1e-16) by about 10^6 over the
-    ringing, so the density field is held to 1e-9 (measured 2.2e-10 at
-    50,000 steps), the radius history and mass to 1e-10 and the wall-pressure
-    peak to 1e-12 at the oracle's step.  Binary64 thus follows the oracle five
-    orders of magnitude inside the binary32 bar where binary32 leaves it
+    """The same 50,000-step collapses in binary64 (the fused single-step
+    kernel) against the oracle's runs: the flow amplifies the two programs'
+    different rounding orders (unit roundoff 1.1e-16) by up to about 10^7
+    over the ringing (density field 2.2e-10 and 1.0e-9 at 50,000 steps for
+    delta 0.02 and 0.01), so the field is held to 1e-8, four orders of
+    magnitude inside the binary32 bar, the radius history and mass to 1e-10
+    and the wall-pressure peak to 1e-12 at the oracle's step.  Binary64
+    follows the oracle there where binary32 leaves the bar
     (test_collapse_density_field_late): that failure is the storage
     precision's, not a difference of model or path."""
     g = _load(COLLAPSES[case])
@@ -322,4 +329,4 @@ def test_collapse_binary64_follows_the_oracle_over_the_whole_horizon(case):
           flush=True)
     assert er < 1e-10 and em < 1e-10
     assert ew < 1e-12 and d["wall_p_step"] == int(g["wall_p_step"])
-    assert max(field.values()) < 1e-9
+    assert max(field.values()) < 1e-8
