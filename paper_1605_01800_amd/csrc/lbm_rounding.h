@@ -57,8 +57,8 @@ LBM_ROUNDING_FN float stochastic_sum(float a, float b, unsigned key)
     const float s = a + b;
     const float bp = s - a;
     const float err = (a - (s - bp)) + (b - bp);               // a + b = s + err exactly
-    const int step = (err > 0.0f) == (s > 0.0f) ? 1 : -1;      // toward err, in the encoding
-    const float o = __builtin_bit_cast(float, __builtin_bit_cast(int, s) + step);
+    const unsigned step = (err > 0.0f) == (s > 0.0f) ? 1u : ~0u;   // toward err, in the encoding
+    const float o = __builtin_bit_cast(float, __builtin_bit_cast(unsigned, s) + step);   // wraps
     const float gap = __builtin_fabsf(o - s);
     const float u = (float)(key >> 8) * 0x1p-24f;
     return u * gap < __builtin_fabsf(err) ? o : s;
