@@ -113,3 +113,40 @@ def test_served_binary32_results_within_1e4_of_binary64():
         print(e, flush=True)
         assert e["radius"] < 1e-4 and e["mass"] < 1e-4
         assert e["wall_p"] is None or e["wall_p"] < 1e-4
+
+
+def test_served_results_against_the_oracle():
+    """Every served result (binary32, the two-step kernel, two batches with
+    write-through stores, several requests resident at once, as the benchmark
+    serves) against the binary64 CPU oracle stepping the same request alone:
+    density field (max norm, relative to the largest density), bubble radius
+    and total mass within the binary32 bar of 1e-4; each result's errors are
+    printed."""
+    import numpy as np
+    from oracle import coexist, diagnostics, stepper as ostep
+    from tests.helpers import oracle_params
+    variant = L.variant_names().index("twostep-58x32")
+    be = GpuBackend(precision="fp32", max_instances=8, max_tiles=1 << 14, variant=variant, keep_state=True,
+                    n_batches=2, write_through=True)
+    srv = Server(be, budget_bytes=10 ** 9, max_slots=8, chunk_steps=128)
+    results, _ = srv.run(_requests())
+    be.close()
+    for r, q in zip(sorted(results, key=lambda r: r.id), _requests()):
+        assert r.id == q.id and not r.failed and r.diag["step"] == q.steps
+        p = L.make_params(q.nx, q.ny, T_over_Tc=q.T_over_Tc, walls=q.walls, precision="fp64", tau_nu=q.tau_nu)
+        P = oracle_params(p)
+        rg, rl, _ = coexist.maxwell(p.T)
+        rho0 = ostep.init_density(P, bubbles=q.bubbles, rho_l=rl, rho_g=rg, W=q.W, delta=q.delta,
+                                  noise_amp=q.noise_amp, seed=q.seed)
+        f = ostep.init_populations(P, rho0)
+        assert ostep.step(P, f, q.steps) == 0
+        rho_o = ostep.density(P, f)
+        rho_s = r.state.double().sum(0).numpy()
+        e_rho = float(np.max(np.abs(rho_s - rho_o)) / np.max(np.abs(rho_o)))
+        rad_o = diagnostics.bubble_radius(rho_o, rl, rg)
+        e_rad = abs(r.diag["radius"][0] - rad_o) / rad_o
+        m_o = diagnostics.neumaier_sum(rho_o)
+        e_m = abs(r.diag["mass"] - m_o) / m_o
+        print("request %d (%dx%d, %d steps): density %.2e radius %.2e mass %.2e"
+              % (q.id, q.nx, q.ny, q.steps, e_rho, e_rad, e_m), flush=True)
+        assert e_rho < 1e-4 and e_rad < 1e-4 and e_m < 1e-4
